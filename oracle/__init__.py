@@ -1,0 +1,297 @@
+"""CPU oracle for depth-map fusion by TGV minimisation -- TEST INFRASTRUCTURE.
+
+A plain, slow, obviously correct reference (``oracle.c``: canonical
+binary32 pyramids and histogram votes per Algorithm 1; float64 TGV-L1
+energy of Eq. 2/3 and its primal-dual minimisation) plus a few closed
+forms in numpy.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the GPU library never does,
+and this package imports nothing from it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (canonical float flags)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u16p = np.ctypeslib.ndpointer(dtype=np.uint16, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        c_int, c_long, c_float, c_double = ctypes.c_int, ctypes.c_long, ctypes.c_float, ctypes.c_double
+        L.or_pyr_levels.argtypes = [c_int, c_int]
+        L.or_pyr_levels.restype = c_int
+        L.or_pyr_floats.argtypes = [c_int, c_int]
+        L.or_pyr_floats.restype = c_long
+        L.or_pyramid.argtypes = [_f32p, c_int, c_int, _f32p]
+        L.or_pyramid.restype = None
+        L.or_vote_bin.argtypes = [_f32p, c_int, c_int, _f32p, _f32p, _f32p, _f32p, c_float, c_int, c_int, c_int,
+                                  c_float, c_float, c_int, c_int]
+        L.or_vote_bin.restype = c_int
+        L.or_histograms.argtypes = [_f32p, c_int, _f32p, _f32p, _f32p, _i32p, _i32p, _f32p, c_float, c_int, c_int,
+                                    c_int, c_float, c_float, c_int, c_int, ctypes.c_void_p, c_long, _u16p]
+        L.or_histograms.restype = c_long
+        L.or_apply_K.argtypes = [c_int, c_int, c_int, _f64p, _f64p, _f64p, _f64p]
+        L.or_apply_K.restype = None
+        L.or_apply_KT.argtypes = [c_int, c_int, c_int, _f64p, _f64p, _f64p, _f64p]
+        L.or_apply_KT.restype = None
+        L.or_prox.argtypes = [c_double, _f64p, _f64p, c_int, c_double, c_double]
+        L.or_prox.restype = c_double
+        L.or_solve.argtypes = [c_int, c_int, c_int, c_int, _u16p, c_int, _f64p, c_double, c_double, c_double,
+                               c_double, c_double, c_int, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
+        L.or_solve.restype = None
+        L.or_primal_energy.argtypes = [c_int, c_int, c_int, c_int, _u16p, c_int, _f64p, c_double, c_double, c_double,
+                                       _f64p, _f64p, _f64p]
+        L.or_primal_energy.restype = c_double
+        L.or_dual_energy.argtypes = [c_int, c_int, c_int, c_int, _u16p, c_int, _f64p, c_double, c_double, _f64p,
+                                     _f64p, _f64p]
+        L.or_dual_energy.restype = c_double
+        L.or_norm_K2.argtypes = [c_int, c_int, c_int, c_int, ctypes.c_uint64]
+        L.or_norm_K2.restype = c_double
+        _lib = L
+    return _lib
+
+
+# ----------------------------------------------------------------------------
+# pyramids and histograms
+# ----------------------------------------------------------------------------
+def pyr_levels(W: int, H: int) -> int:
+    return int(lib().or_pyr_levels(W, H))
+
+
+def pyr_floats(W: int, H: int) -> int:
+    return int(lib().or_pyr_floats(W, H))
+
+
+def pyramid(depth: np.ndarray) -> np.ndarray:
+    """Pyramid of one depth map [H, W] -> all levels back to back (float32)."""
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    H, W = d.shape
+    out = np.empty(pyr_floats(W, H), dtype=np.float32)
+    lib().or_pyramid(d, W, H, out)
+    return out
+
+
+def pyramid_levels(pyr: np.ndarray, W: int, H: int):
+    """Split a packed pyramid into a list of [H_l, W_l] arrays."""
+    out, off = [], 0
+    w, h = W, H
+    while True:
+        out.append(pyr[off:off + w * h].reshape(h, w))
+        off += w * h
+        if w == 1 and h == 1:
+            break
+        w, h = (w + 1) >> 1, (h + 1) >> 1
+    return out
+
+
+def pyramids(depth: np.ndarray) -> np.ndarray:
+    """Pyramids of a stack of depth maps [n, H, W], concatenated."""
+    return np.concatenate([pyramid(depth[k]) for k in range(depth.shape[0])])
+
+
+def bins_params(grid, num_bins=7, rule=0, delta=None, eta_over_delta=3.0):
+    """Default binning: delta = 3 h (6 times the voxel radius h/2, Sec. 3.1)."""
+    if delta is None:
+        delta = float(np.float32(3.0) * np.float32(grid.h))
+    return dict(num_bins=int(num_bins), rule=int(rule), delta=float(np.float32(delta)),
+                eta_over_delta=float(np.float32(eta_over_delta)))
+
+
+def histograms(scene, pyr=None, vox=None, num_bins=7, rule=0, delta=None, eta_over_delta=3.0):
+    """uint16 [count, 8] histograms of all voxels (vox None) or of the given
+    linear voxel indices, and the largest per-voxel vote total."""
+    cams, g = scene.cams, scene.grid
+    if pyr is None:
+        pyr = pyramids(scene.depth)
+    bp = bins_params(g, num_bins, rule, delta, eta_over_delta)
+    if vox is None:
+        count, vptr = g.nvox, None
+        vox_arr = None
+    else:
+        vox_arr = np.ascontiguousarray(vox, dtype=np.int64)
+        count, vptr = vox_arr.size, vox_arr.ctypes.data
+    out = np.zeros((count, 8), dtype=np.uint16)
+    nx, ny, nz = (int(v) for v in g.n)
+    mx = lib().or_histograms(np.ascontiguousarray(pyr, dtype=np.float32), len(cams),
+                             np.ascontiguousarray(cams.R.reshape(-1), dtype=np.float32),
+                             np.ascontiguousarray(cams.t.reshape(-1), dtype=np.float32),
+                             np.ascontiguousarray(cams.intr.reshape(-1), dtype=np.float32),
+                             np.ascontiguousarray(cams.wh.reshape(-1), dtype=np.int32),
+                             np.ascontiguousarray(cams.vote, dtype=np.int32),
+                             np.ascontiguousarray(g.origin, dtype=np.float32), float(g.h), nx, ny, nz,
+                             bp["delta"], bp["eta_over_delta"], bp["num_bins"], bp["rule"], vptr, count, out)
+    return out, int(mx)
+
+
+def vote_bin(scene, pyr_cam: np.ndarray, cam: int, i: int, j: int, k: int, num_bins=7, rule=0, delta=None,
+             eta_over_delta=3.0) -> int:
+    cams, g = scene.cams, scene.grid
+    bp = bins_params(g, num_bins, rule, delta, eta_over_delta)
+    W, H = (int(v) for v in cams.wh[cam])
+    return int(lib().or_vote_bin(np.ascontiguousarray(pyr_cam, dtype=np.float32), W, H,
+                                 np.ascontiguousarray(cams.R[cam].reshape(-1), dtype=np.float32),
+                                 np.ascontiguousarray(cams.t[cam], dtype=np.float32),
+                                 np.ascontiguousarray(cams.intr[cam], dtype=np.float32),
+                                 np.ascontiguousarray(g.origin, dtype=np.float32), float(g.h), i, j, k,
+                                 bp["delta"], bp["eta_over_delta"], bp["num_bins"], bp["rule"]))
+
+
+# ----------------------------------------------------------------------------
+# solver
+# ----------------------------------------------------------------------------
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def apply_K(u, v, shape):
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    kp = np.zeros(3 * n)
+    kq = np.zeros(6 * n)
+    lib().or_apply_K(nx, ny, nz, _c64(u).ravel(), _c64(v).ravel(), kp, kq)
+    return kp, kq
+
+
+def apply_KT(p, q, shape):
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    gu = np.zeros(n)
+    gv = np.zeros(3 * n)
+    lib().or_apply_KT(nx, ny, nz, _c64(p).ravel(), _c64(q).ravel(), gu, gv)
+    return gu, gv
+
+
+def prox(ut, hk, ck, tau, lam):
+    hk = _c64(hk)
+    ck = _c64(ck)
+    return float(lib().or_prox(float(ut), hk, ck, int(hk.size), float(tau), float(lam)))
+
+
+def norm_K2(shape, iters=200, seed=1):
+    nx, ny, nz = shape
+    return float(lib().or_norm_K2(nx, ny, nz, iters, seed))
+
+
+def f32(x) -> float:
+    """A parameter as the GPU library sees it (rounded to binary32)."""
+    return float(np.float32(x))
+
+
+class State:
+    """Primal-dual state of the oracle: u, v (3), p (3), q (6), ubar, vbar (float64, component-major)."""
+
+    def __init__(self, shape, u0):
+        nx, ny, nz = shape
+        n = nx * ny * nz
+        self.shape = (nx, ny, nz)
+        self.u = _c64(u0).ravel().copy()
+        self.ubar = self.u.copy()
+        self.v = np.zeros(3 * n)
+        self.vbar = np.zeros(3 * n)
+        self.p = np.zeros(3 * n)
+        self.q = np.zeros(6 * n)
+
+    def copy(self):
+        s = State.__new__(State)
+        s.shape = self.shape
+        for k in ("u", "ubar", "v", "vbar", "p", "q"):
+            setattr(s, k, getattr(self, k).copy())
+        return s
+
+
+def centers64(centers, num_bins):
+    return _c64(np.asarray(centers, dtype=np.float32)[:num_bins].astype(np.float64))
+
+
+def solve(hist, shape, centers, iters, alpha0=2.0, alpha1=1.0, lam=1.0, tau=None, sigma=None, halo=0,
+          num_bins=7, u0=None, state: State = None) -> State:
+    """Run `iters` primal-dual iterations (fresh start from u0, default 0,
+    unless a state is given, which is advanced in place and returned).
+    Parameters are rounded to binary32 first, as the GPU library takes them."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    if tau is None:
+        tau = 1.0 / np.sqrt(12.0)
+    if sigma is None:
+        sigma = tau
+    if state is None:
+        state = State(shape, np.zeros(n) if u0 is None else u0)
+    h = np.ascontiguousarray(hist, dtype=np.uint16).reshape(n, 8)
+    lib().or_solve(nx, ny, nz, int(halo), h, int(num_bins), centers64(centers, num_bins), f32(alpha0), f32(alpha1),
+                   f32(lam), f32(tau), f32(sigma), int(iters), state.u, state.v, state.p, state.q, state.ubar,
+                   state.vbar)
+    return state
+
+
+def primal_energy(hist, shape, centers, u, v, alpha0=2.0, alpha1=1.0, lam=1.0, halo=0, num_bins=7):
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    parts = np.zeros(3)
+    e = lib().or_primal_energy(nx, ny, nz, int(halo), np.ascontiguousarray(hist, dtype=np.uint16).reshape(n, 8),
+                               int(num_bins), centers64(centers, num_bins), f32(alpha0), f32(alpha1), f32(lam),
+                               _c64(u).ravel(), _c64(v).ravel(), parts)
+    return float(e), parts
+
+
+VBOUND = 2.0 * np.sqrt(3.0)
+
+
+def dual_energy(hist, shape, centers, u, p, q, lam=1.0, halo=0, num_bins=7, vbound=VBOUND):
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    return float(lib().or_dual_energy(nx, ny, nz, int(halo), np.ascontiguousarray(hist, dtype=np.uint16).reshape(n, 8),
+                                      int(num_bins), centers64(centers, num_bins), f32(lam), float(vbound),
+                                      _c64(u).ravel(), _c64(p).ravel(), _c64(q).ravel()))
+
+
+def gap(hist, shape, centers, st: State, alpha0=2.0, alpha1=1.0, lam=1.0, halo=0, num_bins=7):
+    """(P, D, relative gap (P - D) / max(P, 1))."""
+    P, _ = primal_energy(hist, shape, centers, st.u, st.v, alpha0, alpha1, lam, halo, num_bins)
+    D = dual_energy(hist, shape, centers, st.u, st.p, st.q, lam, halo, num_bins)
+    return P, D, (P - D) / max(P, 1.0)
+
+
+# ----------------------------------------------------------------------------
+# closed forms (numpy)
+# ----------------------------------------------------------------------------
+def weighted_median_interval(hk, ck):
+    """Minimisers [lo, hi] of sum_k h_k |w - c_k| (the weighted median); for
+    an odd total weight lo == hi.  Empty histograms give (-inf, inf)."""
+    hk = np.asarray(hk, dtype=np.int64)
+    ck = np.asarray(ck, dtype=np.float64)
+    W = int(hk.sum())
+    if W == 0:
+        return -np.inf, np.inf
+    expanded = np.repeat(ck, hk)  # sorted because centres ascend
+    if W % 2 == 1:
+        m = float(expanded[W // 2])
+        return m, m
+    return float(expanded[W // 2 - 1]), float(expanded[W // 2])

@@ -1,0 +1,337 @@
+"""Pins of the oracle's TGV-L1 solver (Eq. 1-3, primal-dual method of Sec. 3.2)
+against what the mathematics fixes: operator identities, closed-form
+minimisers, an exact LP in 1-D, an independent smoothed solver in 3-D and
+weak duality.  CPU only."""
+import numpy as np
+import pytest
+import torch
+from scipy.optimize import linprog, minimize
+
+import oracle
+import scenes
+
+C7 = scenes.default_bins(7, 0)
+C64 = C7[:7].astype(np.float64)
+
+
+def rand_hist(shape, rng, odd=True, lo=1, hi=9, fully=True):
+    n = int(np.prod(shape))
+    h = np.zeros((n, 8), dtype=np.uint16)
+    for x in range(n):
+        if not fully and rng.random() < 0.3:
+            continue
+        tot = int(rng.integers(lo, hi + 1))
+        if odd and tot % 2 == 0:
+            tot += 1
+        b = rng.integers(0, 7, size=tot)
+        h[x, :7] = np.bincount(b, minlength=7)
+    return h
+
+
+# ---------------------------------------------------------------------------
+# operators (Eq. 2, Eq. 3)
+# ---------------------------------------------------------------------------
+def test_adjointness_random():
+    rng = np.random.default_rng(1)
+    shape = (5, 4, 3)
+    n = 60
+    u, v = rng.normal(size=n), rng.normal(size=3 * n)
+    p, q = rng.normal(size=3 * n), rng.normal(size=6 * n)
+    kp, kq = oracle.apply_K(u, v, shape)
+    gu, gv = oracle.apply_KT(p, q, shape)
+    w = np.repeat([1.0, 1.0, 1.0, 2.0, 2.0, 2.0], n)  # weighted inner product on q
+    lhs = kp @ p + (w * kq) @ q
+    rhs = u @ gu + v @ gv
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+
+
+def test_K_closed_forms():
+    nx, ny, nz = 6, 5, 4
+    n = nx * ny * nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    # u = x^2, v = 0: forward difference 2x + 1 except the last x-cell (dropped)
+    kp, kq = oracle.apply_K((x ** 2).astype(float), np.zeros(3 * n), (nx, ny, nz))
+    np.testing.assert_array_equal(kp[:n], np.where(x < nx - 1, 2 * x + 1, 0))
+    assert not kp[n:].any() and not kq.any()
+    # u = 0, v_x = y: E_xy = d-_y v_x / 2 = 1/2 where y > 0
+    v = np.zeros(3 * n)
+    v[:n] = y
+    kp, kq = oracle.apply_K(np.zeros(n), v, (nx, ny, nz))
+    np.testing.assert_array_equal(kq[3 * n:4 * n], np.where(y > 0, 0.5, 0.0))
+    assert not kq[:3 * n].any() and not kq[4 * n:].any()
+    np.testing.assert_array_equal(kp[:n], np.where(x < nx - 1, -y, 0))
+    # v_z = z^2: E_zz = z^2 - (z-1)^2 = 2z - 1 where z > 0
+    v = np.zeros(3 * n)
+    v[2 * n:] = z ** 2
+    kp, kq = oracle.apply_K(np.zeros(n), v, (nx, ny, nz))
+    np.testing.assert_array_equal(kq[2 * n:3 * n], np.where(z > 0, 2 * z - 1, 0))
+
+
+def test_affine_u_with_matching_v_has_zero_K():
+    nx, ny, nz = 7, 6, 5
+    n = nx * ny * nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    a, b, c, d = 0.375, -0.25, 0.125, 0.5
+    u = (a * x + b * y + c * z + d).ravel()
+    v = np.concatenate([np.full(n, a), np.full(n, b), np.full(n, c)])
+    kp, kq = oracle.apply_K(u, v, (nx, ny, nz))
+    assert not kp.any() and not kq.any()
+
+
+def test_operator_norm_bound():
+    L2 = oracle.norm_K2((12, 12, 12), iters=400)
+    assert 15.0 < L2 <= 16.0 + 1e-9
+
+
+# ---------------------------------------------------------------------------
+# proximal map of the histogram data term
+# ---------------------------------------------------------------------------
+def _prox_obj(w, ut, hk, ck, tau, lam):
+    return (w - ut) ** 2 / (2 * tau) + lam * np.sum(hk[None, :] * np.abs(w[:, None] - ck[None, :]), axis=1)
+
+
+def test_prox_against_dense_search():
+    rng = np.random.default_rng(2)
+    grid = np.linspace(-4, 4, 160001)
+    for _ in range(300):
+        hk = rng.integers(0, 6, size=7).astype(float)
+        ut = rng.uniform(-3, 3)
+        tau, lam = rng.uniform(0.05, 1.0), rng.uniform(0.0, 2.0)
+        w = oracle.prox(ut, hk, C64, tau, lam)
+        vals = _prox_obj(grid, ut, hk, C64, tau, lam)
+        wg = grid[np.argmin(vals)]
+        assert abs(w - wg) <= 6e-5
+        assert _prox_obj(np.array([w]), ut, hk, C64, tau, lam)[0] <= vals.min() + 1e-12
+
+
+def test_prox_limits():
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        hk = rng.integers(0, 6, size=7).astype(float)
+        if hk.sum() % 2 == 0:
+            hk[3] += 1
+        ut = rng.uniform(-3, 3)
+        assert oracle.prox(ut, hk, C64, 0.3, 0.0) == ut          # no data weight: identity
+        lo, hi = oracle.weighted_median_interval(hk.astype(int), C64)
+        assert oracle.prox(ut, hk, C64, 1e6, 1.0) == lo          # huge step: the weighted median
+    assert oracle.prox(0.7, np.zeros(7), C64, 0.3, 1.0) == 0.7   # empty histogram
+
+
+# ---------------------------------------------------------------------------
+# solver special cases
+# ---------------------------------------------------------------------------
+def test_alpha_zero_gives_weighted_median():
+    rng = np.random.default_rng(4)
+    shape = (6, 5, 4)
+    hist = rand_hist(shape, rng, odd=True)
+    st = oracle.solve(hist, shape, C7, 200, alpha0=0.0, alpha1=0.0)
+    med = np.array([oracle.weighted_median_interval(hist[x, :7].astype(int), C64)[0] for x in range(hist.shape[0])])
+    np.testing.assert_array_equal(st.u, med)
+    assert not st.p.any() and not st.q.any()
+
+
+def test_constant_histograms_give_constant_median():
+    shape = (6, 5, 4)
+    n = 120
+    hist = np.zeros((n, 8), dtype=np.uint16)
+    hist[:, :7] = [0, 1, 0, 2, 4, 0, 0]  # W = 7, weighted median = c_4 = 1/3
+    st = oracle.solve(hist, shape, C7, 400)
+    np.testing.assert_allclose(st.u, np.float32(C7[4]), atol=1e-9)
+
+
+def test_affine_plane_reproduced_through_histogram_path():
+    # plane at voxel index 3 along z seen head-on: the histogram of voxel k
+    # concentrates at c_{6-k}, i.e. u = 1 - k/3, an affine field of zero TGV
+    # energy; it is the unique minimiser, so the solver must return it
+    sc = scenes.plane_scene(n=(4, 3, 7), z_plane_index=3, n_cams=5)
+    hist, _ = oracle.histograms(sc)
+    H = hist.reshape(7, 3, 4, 8)
+    for k in range(7):
+        assert H[k, :, :, 6 - k].min() == 5 and H[k].sum() == 5 * 12
+    shape = (4, 3, 7)
+    st = oracle.solve(hist, shape, C7, 3000)
+    u = st.u.reshape(7, 3, 4)
+    expect = np.array([np.float64(C7[6 - k]) for k in range(7)])
+    np.testing.assert_allclose(u, np.broadcast_to(expect[:, None, None], u.shape), atol=1e-6)
+    P, parts = oracle.primal_energy(hist, shape, C7, st.u, st.v)
+    assert P < 1e-5
+
+
+def test_frozen_halo_and_bitwise_resume():
+    rng = np.random.default_rng(5)
+    shape = (8, 7, 6)
+    n = 336
+    hist = rand_hist(shape, rng, fully=False)
+    u0 = rng.uniform(-1, 1, size=n)
+    a = oracle.solve(hist, shape, C7, 60, halo=2, u0=u0)
+    b = oracle.solve(hist, shape, C7, 25, halo=2, u0=u0)
+    b = oracle.solve(hist, shape, C7, 35, halo=2, state=b)
+    for k in ("u", "v", "p", "q", "ubar", "vbar"):
+        np.testing.assert_array_equal(getattr(a, k), getattr(b, k))
+    z, y, x = np.meshgrid(np.arange(6), np.arange(7), np.arange(8), indexing="ij")
+    frozen = ((x < 2) | (x >= 6) | (y < 2) | (y >= 5) | (z < 2) | (z >= 4)).ravel()
+    np.testing.assert_array_equal(a.u[frozen], u0[frozen])
+    assert np.any(a.u[~frozen] != u0[~frozen])
+
+
+# ---------------------------------------------------------------------------
+# exact minimum energy in 1-D (linear program)
+# ---------------------------------------------------------------------------
+def _lp_1d(hist, alpha0, alpha1, lam):
+    """min alpha1 sum_i |u_{i+1} - u_i - v_i| + alpha0 sum_i |v_i - v_{i-1}| + lam sum h|u - c|
+    (the discrete Eq. 2 on an N x 1 x 1 block: y/z differences are dropped
+    and v_y = v_z = 0 is optimal) as an LP solved by HiGHS."""
+    N = hist.shape[0]
+    terms = []  # (coefficient dict over u/v, constant, weight)
+    for i in range(N - 1):
+        terms.append(({("u", i + 1): 1.0, ("u", i): -1.0, ("v", i): -1.0}, 0.0, alpha1))
+    for i in range(1, N):
+        terms.append(({("v", i): 1.0, ("v", i - 1): -1.0}, 0.0, alpha0))
+    for i in range(N):
+        for k in range(7):
+            if hist[i, k]:
+                terms.append(({("u", i): 1.0}, -float(C64[k]), lam * float(hist[i, k])))
+    nv = 2 * N + len(terms)
+    col = lambda key: key[1] if key[0] == "u" else N + key[1]
+    c = np.zeros(nv)
+    A, b = [], []
+    for t, (coef, const, wt) in enumerate(terms):
+        e = 2 * N + t
+        c[e] = wt
+        for sgn in (1.0, -1.0):
+            row = np.zeros(nv)
+            for key, val in coef.items():
+                row[col(key)] = sgn * val
+            row[e] = -1.0
+            A.append(row)
+            b.append(-sgn * const)
+    bounds = [(None, None)] * (2 * N) + [(0, None)] * len(terms)
+    res = linprog(c, A_ub=np.array(A), b_ub=np.array(b), bounds=bounds, method="highs")
+    assert res.status == 0
+    return res.fun, res.x[:N]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_1d_energy_matches_exact_lp(seed):
+    rng = np.random.default_rng(10 + seed)
+    N = 14
+    hist = rand_hist((N, 1, 1), rng, odd=True, lo=1, hi=5)
+    a0, a1, lam = oracle.f32(2.0), oracle.f32(1.0), oracle.f32(1.0)
+    E_lp, u_lp = _lp_1d(hist, a0, a1, lam)
+    st = oracle.solve(hist, (N, 1, 1), C7, 20000)
+    P, _ = oracle.primal_energy(hist, (N, 1, 1), C7, st.u, st.v)
+    assert P >= E_lp - 1e-9 * max(1.0, E_lp)
+    assert P - E_lp <= 1e-8 * max(1.0, E_lp)
+
+
+# ---------------------------------------------------------------------------
+# 3-D: independent smoothed solver, weak duality and the gap
+# ---------------------------------------------------------------------------
+def _smoothed_minimiser(hist, shape, alpha0, alpha1, lam, eps_list=(1e-2, 1e-4, 1e-6)):
+    """Minimise a smoothed Eq. 2 (|.| -> sqrt(.^2 + eps^2)) with L-BFGS and
+    continuation in eps; an algorithm unrelated to the primal-dual scheme."""
+    nx, ny, nz = shape
+    h = torch.tensor(hist[:, :7].astype(np.float64)).reshape(nz, ny, nx, 7)
+    c = torch.tensor(C64)
+
+    def fwd(u, ax):  # forward difference along a (z, y, x) axis, 0 on the last slice
+        d = torch.diff(u, dim=ax)
+        pad = list(u.shape)
+        pad[ax] = 1
+        return torch.cat([d, torch.zeros(pad, dtype=u.dtype)], dim=ax)
+
+    def bwd(w, ax):  # backward difference, 0 on the first slice
+        d = torch.diff(w, dim=ax)
+        pad = list(w.shape)
+        pad[ax] = 1
+        return torch.cat([torch.zeros(pad, dtype=w.dtype), d], dim=ax)
+
+    axes = {0: 2, 1: 1, 2: 0}  # x, y, z -> tensor axis
+
+    def energy(z, eps):
+        u = z[: nx * ny * nz].reshape(nz, ny, nx)
+        v = z[nx * ny * nz:].reshape(3, nz, ny, nx)
+        mask = [torch.ones_like(u) for _ in range(3)]
+        for i in range(3):
+            m = mask[i]
+            idx = [slice(None)] * 3
+            idx[axes[i]] = -1
+            m[tuple(idx)] = 0
+        g = [mask[i] * (fwd(u, axes[i]) - v[i]) for i in range(3)]
+        t1 = torch.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2 + eps ** 2).sum()
+        D = [[bwd(v[i], axes[j]) for j in range(3)] for i in range(3)]
+        E2 = (D[0][0] ** 2 + D[1][1] ** 2 + D[2][2] ** 2
+              + 2 * (0.5 * (D[0][1] + D[1][0])) ** 2 + 2 * (0.5 * (D[0][2] + D[2][0])) ** 2
+              + 2 * (0.5 * (D[1][2] + D[2][1])) ** 2)
+        t0 = torch.sqrt(E2 + eps ** 2).sum()
+        td = (h * torch.sqrt((u[..., None] - c) ** 2 + eps ** 2)).sum()
+        return alpha1 * t1 + alpha0 * t0 + lam * td
+
+    torch_threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    z = np.zeros(4 * nx * ny * nz)
+    for eps in eps_list:
+        def fg(zz):
+            t = torch.tensor(zz, requires_grad=True)
+            e = energy(t, eps)
+            e.backward()
+            return e.item(), t.grad.numpy().copy()
+        res = minimize(fg, z, jac=True, method="L-BFGS-B", options=dict(maxiter=4000, maxcor=30, ftol=1e-15,
+                                                                         gtol=1e-12))
+        z = res.x
+    torch.set_num_threads(torch_threads)
+    n = nx * ny * nz
+    u = z[:n]
+    v = z[n:]
+    return u, v
+
+
+@pytest.mark.parametrize("seed", [0])
+def test_4cube_cp_beats_independent_smoothed_solver(seed):
+    rng = np.random.default_rng(20 + seed)
+    shape = (4, 4, 4)
+    hist = rand_hist(shape, rng, odd=True, lo=1, hi=6)
+    a0, a1, lam = oracle.f32(2.0), oracle.f32(1.0), oracle.f32(1.0)
+    st = oracle.solve(hist, shape, C7, 20000)
+    P_cp, _ = oracle.primal_energy(hist, shape, C7, st.u, st.v)
+    D_cp = oracle.dual_energy(hist, shape, C7, st.u, st.p, st.q)
+    u_s, v_s = _smoothed_minimiser(hist, shape, a0, a1, lam)
+    P_s, _ = oracle.primal_energy(hist, shape, C7, u_s, v_s)
+    # the primal-dual result is at least as good as the independent optimum ...
+    assert P_cp <= P_s + 1e-6 * P_s
+    assert abs(P_cp - P_s) <= 1e-3 * P_s
+    # ... and the dual bound from (p, q) lower-bounds the independent solution
+    # (weak duality across two unrelated codes; both solutions lie in the box)
+    assert np.abs(u_s).max() <= 1.0 + 1e-6
+    assert D_cp <= P_s + 1e-9
+
+
+@pytest.mark.parametrize("shape,iters", [((4, 4, 4), 20000), ((8, 8, 8), 50000)])
+def test_gap_closes_on_fully_observed_blocks(shape, iters):
+    rng = np.random.default_rng(7)
+    hist = rand_hist(shape, rng, odd=True)
+    st = oracle.solve(hist, shape, C7, iters)
+    P, D, g = oracle.gap(hist, shape, C7, st)
+    assert D <= P + 1e-9
+    assert g < 1e-6
+
+
+def test_weak_duality_random_feasible_points():
+    rng = np.random.default_rng(8)
+    shape = (5, 4, 3)
+    n = 60
+    hist = rand_hist(shape, rng, fully=False)
+    for _ in range(20):
+        u = rng.uniform(-1, 1, n)
+        v = rng.normal(size=3 * n)
+        v = v.reshape(3, n)
+        v = (v / np.maximum(1.0, np.linalg.norm(v, axis=0) / oracle.VBOUND)).ravel()
+        p = rng.normal(size=3 * n).reshape(3, n)
+        p = (p / np.maximum(1.0, np.linalg.norm(p, axis=0) / 1.0)).ravel()
+        q = rng.normal(size=6 * n).reshape(6, n)
+        qn = np.sqrt((q[:3] ** 2).sum(0) + 2 * (q[3:] ** 2).sum(0))
+        q = (q / np.maximum(1.0, qn / 2.0)).ravel()
+        P, _ = oracle.primal_energy(hist, shape, C7, u, v)
+        D = oracle.dual_energy(hist, shape, C7, u, p, q)
+        assert D <= P + 1e-9
