@@ -1,0 +1,211 @@
+/*
+ * tgv.h -- C ABI of libtgv, the MI355X (gfx950) library for depth-map fusion
+ * by TGV minimisation (Out-of-Core Surface Reconstruction via Global TGV
+ * Minimization, 2021).
+ *
+ * The library computes, on one voxel block of the octree at a time:
+ *   - depth-map mipmap pyramids (Sec. 3.4),
+ *   - per-voxel vote histograms from the depth maps (Sec. 3.4, Algorithm 1),
+ *   - the indicator field u minimising the TGV-L1 energy (Eq. 2 with the
+ *     symmetric gradient of Eq. 3 and the data weight lambda of Eq. 1) by the
+ *     first-order primal-dual method of Sec. 3.2, with u frozen on a border
+ *     layer (Sec. 4.5, Fig. 7), and the energy / duality-gap statistics.
+ *
+ * Conventions for every call:
+ *   - Array pointers are DEVICE pointers unless the name ends in _host.
+ *     The caller allocates and frees them; the library never frees caller
+ *     memory and keeps no pointer to it after the call returns.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
+ *     NULL = the null stream) unless documented as synchronising.
+ *   - Voxel layout: index x + nx * (y + ny * z) (x fastest).
+ *   - Errors are returned as tgv_status; no exception crosses the ABI.
+ *     tgv_last_error(ctx) gives a message for the last failing call.
+ *   - One context per host thread; a context is not re-entrant.
+ *   - Depth maps hold the camera-frame z of the surface seen through each
+ *     pixel; values that are not finite or <= 0 mean "no sample".
+ *   - Camera model: Xc = R X + t (R row-major); pixel column i covers
+ *     [i, i+1); px = fx Xc/Zc + cx, py = fy Yc/Zc + cy.
+ */
+#ifndef TGV_H
+#define TGV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TGV_OK = 0,
+    TGV_E_INVAL = 1,       /* bad argument (null pointer, bad size, bad parameter) */
+    TGV_E_NOMEM = 2,       /* device allocation failed */
+    TGV_E_DEVICE = 3,      /* a HIP runtime call failed */
+    TGV_E_OVERFLOW = 4,    /* a histogram count could exceed 65535 */
+    TGV_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+} tgv_status;
+
+/* One pinhole camera (80 bytes). vote: weight of its votes (1 for stereo
+ * depth maps, 5 for near noise-free LIDAR scans, Algorithm 1). */
+typedef struct {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    int32_t vote;
+    int32_t reserved;
+} tgv_camera;
+
+/* A regular voxel block: voxel (i, j, k) has centre origin + (idx + 1/2) h.
+ * Voxels closer than `halo` cells to a face keep u frozen during a solve
+ * (set B of Fig. 7); 0 <= 2 halo < min(nx, ny, nz). */
+typedef struct {
+    float origin[3];
+    float h;
+    int32_t nx, ny, nz;
+    int32_t halo;
+} tgv_grid;
+
+/* Histogram binning (Algorithm 1).  delta: width of the near-surface band in
+ * world units (6 voxel radii = 3 h by default, Sec. 3.1); votes with
+ * depth - z < -eta_over_delta * delta are dropped (occluded region).
+ * rule 0: nearest of num_bins centres spread evenly over [-1, 1] (ends
+ * included); rule 1: floor(((a + 1) / 2) num_bins) with a = 1 folded into
+ * the last bin.  centers[0..num_bins-1] ascending are the values the solver
+ * uses for each bin; 1 <= num_bins <= 8. */
+typedef struct {
+    int32_t num_bins;
+    int32_t rule;
+    float centers[8];
+    float delta;
+    float eta_over_delta;
+} tgv_bins;
+
+/* Storage precision of v, p, q in the solver state (u is always float32;
+ * arithmetic is float32 in every mode). */
+enum { TGV_STORE_F32 = 0, TGV_STORE_F16 = 1, TGV_STORE_BF16 = 2 };
+
+/* Kernel schedule of a solve: FUSED runs one kernel per iteration (primal
+ * then dual in one pass); SPLIT runs the dual and the primal update as two
+ * kernels.  Both produce bit-identical results. */
+enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1 };
+
+/* Solver parameters (Eq. 2, Sec. 3.2).  tau, sigma: primal and dual step
+ * sizes (> 0); iters >= 0 primal-dual iterations. */
+typedef struct {
+    float alpha0, alpha1, lambda;
+    float tau, sigma;
+    int32_t iters;
+    int32_t storage;   /* TGV_STORE_* */
+    int32_t schedule;  /* TGV_SCHED_* */
+} tgv_params;
+
+/* Energy statistics of a state, reduced in float64:
+ *   primal = discrete Eq. 2 at (u, v);
+ *   dual   = dual bound of the problem restricted to u in [-1, 1] on free
+ *            voxels and |v| <= 2 sqrt(3) per voxel;
+ *   gap_rel = (primal - dual) / max(primal, 1);
+ *   nonfinite = voxels whose u, v, p or q is not finite. */
+typedef struct {
+    double primal, dual, gap_rel;
+    double parts[3];   /* alpha1 term, alpha0 term, data term of primal */
+    int64_t nonfinite;
+    int64_t iters_done;
+} tgv_stats;
+
+typedef struct tgv_ctx tgv_ctx;
+typedef struct tgv_state tgv_state;
+
+/* Create a context on HIP device `device` (made current for the call).
+ * Returns TGV_E_DEVICE if the device cannot be used. */
+tgv_status tgv_create(int device, tgv_ctx **out);
+/* Release a context and its workspace (synchronises the device). */
+void tgv_destroy(tgv_ctx *ctx);
+/* Message of the last failing call on ctx (never NULL; owned by ctx). */
+const char *tgv_last_error(const tgv_ctx *ctx);
+
+/* ---- depth-map pyramids (Sec. 3.4) ---------------------------------- */
+
+/* Levels of a W x H pyramid: each level halves each side, rounding up,
+ * down to 1 x 1. */
+int32_t tgv_pyramid_levels(int32_t W, int32_t H);
+/* Floats of one camera's packed pyramid (all levels back to back). */
+int64_t tgv_pyramid_floats(int32_t W, int32_t H);
+/* Build the pyramids of n_cams depth maps depth[n_cams][H][W] into
+ * pyr[n_cams][tgv_pyramid_floats(W, H)].  Level 0 is the input with
+ * invalid samples set to 0; a level-(l+1) pixel is the mean of the valid
+ * ones among its (up to four) children, summed in the order (2i,2j),
+ * (2i+1,2j), (2i,2j+1), (2i+1,2j+1), 0 if none is valid. */
+tgv_status tgv_build_pyramids(tgv_ctx *ctx, const float *depth, int32_t n_cams, int32_t W, int32_t H, float *pyr,
+                              void *stream);
+
+/* ---- histograms (Sec. 3.4, Algorithm 1) ------------------------------ */
+
+/* Conservative camera cull for a block (host only): writes to keep_host the
+ * indices of the cameras whose view frustum may contain a voxel centre of
+ * the block, returns their count (or -1 on bad arguments).  Culling never
+ * changes a histogram: dropped cameras cast no vote. */
+int32_t tgv_cull_cameras(const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid, int32_t *keep_host);
+
+/* Vote histograms of every voxel of `grid` from n_cams cameras whose
+ * pyramids are packed in pyr (as written by tgv_build_pyramids, all
+ * cameras width W and height H).  Output hist[nz][ny][nx][8] uint16: slot
+ * k < num_bins counts the votes of bin k, slots >= num_bins are 0.  Per
+ * (voxel, camera): project the voxel centre; no vote if behind the camera,
+ * outside the image, on an invalid sample or further than eta behind the
+ * observed surface; else bin clamp((depth - z) / delta, -1, 1) by `rule`.
+ * The level read is floor(log2(h fx / z)), clamped to the pyramid.  All
+ * arithmetic is IEEE binary32 without contraction, so counts are exact and
+ * reproducible.  TGV_E_OVERFLOW if the votes of the cameras kept by the
+ * cull could sum past 65535. */
+tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32_t W, int32_t H, const tgv_camera *cams_host,
+                                int32_t n_cams, const tgv_grid *grid, const tgv_bins *bins, uint16_t *hist,
+                                void *stream);
+
+/* ---- solver (Eq. 2, Sec. 3.2, Sec. 4.5) ----------------------------- */
+
+/* A resumable solver state for one grid shape and storage precision:
+ * u (current and previous iterate), v (same), p, q (double-buffered),
+ * held in device memory owned by the state. */
+tgv_status tgv_state_create(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, tgv_state **out);
+void tgv_state_destroy(tgv_state *st);
+/* Device bytes a state of this grid and storage uses. */
+int64_t tgv_state_bytes(const tgv_grid *grid, int32_t storage);
+/* Reset to a fresh start: u = u0 (interior initial values and the frozen
+ * border), v = p = q = 0, iteration count 0. */
+tgv_status tgv_state_reset(tgv_ctx *ctx, tgv_state *st, const float *u0, void *stream);
+/* Copy the current fields out as float32 (any pointer may be NULL):
+ * u[n], v[3][n] (current iterate), u_prev[n], v_prev[3][n] (previous
+ * iterate, equal to the current one before the first step), p[3][n],
+ * q[6][n] (q order xx yy zz xy xz yz).  Together they are the whole state:
+ * importing them into a state resumes the iteration bit for bit (for
+ * float32 storage). */
+tgv_status tgv_state_export(tgv_ctx *ctx, const tgv_state *st, float *u, float *v, float *u_prev, float *v_prev,
+                            float *p, float *q, void *stream);
+/* Load a state exported earlier (all six pointers required; values are
+ * rounded to the state's storage precision). */
+tgv_status tgv_state_import(tgv_ctx *ctx, tgv_state *st, const float *u, const float *v, const float *u_prev,
+                            const float *v_prev, const float *p, const float *q, int64_t iters_done, void *stream);
+
+/* Run params->iters primal-dual iterations:
+ *   p <- P_alpha1(p + sigma M.(grad ubar - vbar)),  q <- P_alpha0(q + sigma E(vbar)),
+ *   u <- prox(u + tau div p) on free voxels (u frozen on the border),
+ *   v <- v + tau (M.p + div2 q),  ubar = 2 u_new - u_old,  vbar likewise,
+ * where prox is the proximal map of lambda sum_k hist_k |u - c_k|.
+ * state == NULL: fresh solve from u_io (initial values + frozen border)
+ * in a context-owned state; the result is written back to u_io.
+ * state != NULL: the state is advanced (it must match grid and
+ * params->storage) and u is written to u_io when u_io != NULL.
+ * stats_host != NULL: also reduce the energy statistics of the final
+ * state (this synchronises the stream). */
+tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
+                     const tgv_params *params, float *u_io, tgv_state *state, tgv_stats *stats_host, void *stream);
+
+/* Energy statistics of a state (synchronises the stream). */
+tgv_status tgv_energy(tgv_ctx *ctx, const tgv_state *st, const uint16_t *hist, const tgv_bins *bins,
+                      const tgv_params *params, tgv_stats *stats_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGV_H */

@@ -1,0 +1,376 @@
+"""Python binding of libtgv (MI355X / gfx950 HIP library for depth-map fusion
+by TGV minimisation).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/tgv.h.  Torch tensors carry
+device memory and torch's current stream carries the ordering.  There is no
+CPU fallback: importing this package without the built library, or calling
+it without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtgv.so")
+
+TGV_OK, TGV_E_INVAL, TGV_E_NOMEM, TGV_E_DEVICE, TGV_E_OVERFLOW, TGV_E_UNSUPPORTED = range(6)
+STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
+SCHED_FUSED, SCHED_SPLIT = 0, 1
+STORAGE_NAMES = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
+
+
+class TgvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libtgv status {status}: {msg}")
+        self.status = status
+
+
+# ---------------------------------------------------------------------------
+# ABI structs (must match include/tgv.h)
+# ---------------------------------------------------------------------------
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("vote", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class GridT(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_float * 3), ("h", ctypes.c_float), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("halo", ctypes.c_int32)]
+
+
+class BinsT(ctypes.Structure):
+    _fields_ = [("num_bins", ctypes.c_int32), ("rule", ctypes.c_int32), ("centers", ctypes.c_float * 8),
+                ("delta", ctypes.c_float), ("eta_over_delta", ctypes.c_float)]
+
+
+class ParamsT(ctypes.Structure):
+    _fields_ = [("alpha0", ctypes.c_float), ("alpha1", ctypes.c_float), ("lam", ctypes.c_float),
+                ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("iters", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+
+class StatsT(ctypes.Structure):
+    _fields_ = [("primal", ctypes.c_double), ("dual", ctypes.c_double), ("gap_rel", ctypes.c_double),
+                ("parts", ctypes.c_double * 3), ("nonfinite", ctypes.c_int64), ("iters_done", ctypes.c_int64)]
+
+
+assert ctypes.sizeof(Camera) == 80 and ctypes.sizeof(GridT) == 32 and ctypes.sizeof(BinsT) == 48
+assert ctypes.sizeof(ParamsT) == 32 and ctypes.sizeof(StatsT) == 64
+
+_vp = ctypes.c_void_p
+_SIGS = {
+    "tgv_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    "tgv_destroy": (None, [_vp]),
+    "tgv_last_error": (ctypes.c_char_p, [_vp]),
+    "tgv_pyramid_levels": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
+    "tgv_pyramid_floats": (ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32]),
+    "tgv_build_pyramids": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
+    "tgv_cull_cameras": (ctypes.c_int32, [ctypes.POINTER(Camera), ctypes.c_int32, ctypes.POINTER(GridT),
+                                          ctypes.POINTER(ctypes.c_int32)]),
+    "tgv_build_histograms": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Camera),
+                                            ctypes.c_int32, ctypes.POINTER(GridT), ctypes.POINTER(BinsT), _vp, _vp]),
+    "tgv_state_create": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "tgv_state_destroy": (None, [_vp]),
+    "tgv_state_bytes": (ctypes.c_int64, [ctypes.POINTER(GridT), ctypes.c_int32]),
+    "tgv_state_reset": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "tgv_state_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tgv_state_import": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "tgv_solve": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT),
+                                 _vp, _vp, ctypes.POINTER(StatsT), _vp]),
+    "tgv_energy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT),
+                                  ctypes.POINTER(StatsT), _vp]),
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libtgv.so and declare every exported entry point (no GPU needed)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtgv.so not built at {path}; run __graft_entry__.build() or "
+                          f"python paper_2107_14790_amd/build.py")
+    L = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path == LIB_PATH:
+        _lib = L
+    return L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libtgv takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libtgv takes contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# plain-Python descriptions of the ABI structs
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Bins:
+    num_bins: int = 7
+    rule: int = 0
+    centers: tuple = None      # defaults by rule
+    delta: float = None        # world units; default 3 h
+    eta_over_delta: float = 3.0
+
+    def to_c(self, h: float) -> BinsT:
+        b = BinsT()
+        b.num_bins = self.num_bins
+        b.rule = self.rule
+        if self.centers is None:
+            if self.rule == 0:
+                c = np.linspace(-1.0, 1.0, self.num_bins) if self.num_bins > 1 else np.zeros(1)
+            else:
+                c = -1.0 + (2.0 * np.arange(self.num_bins) + 1.0) / self.num_bins
+        else:
+            c = np.asarray(self.centers, dtype=np.float64)
+        cc = np.full(8, np.inf, dtype=np.float32)
+        cc[:self.num_bins] = c[:self.num_bins].astype(np.float32)
+        for k in range(8):
+            b.centers[k] = float(cc[k])
+        b.delta = float(np.float32(3.0) * np.float32(h)) if self.delta is None else float(self.delta)
+        b.eta_over_delta = float(self.eta_over_delta)
+        return b
+
+    def centers32(self) -> np.ndarray:
+        b = self.to_c(1.0)
+        return np.array([b.centers[k] for k in range(8)], dtype=np.float32)
+
+
+@dataclasses.dataclass
+class Params:
+    alpha0: float = 2.0
+    alpha1: float = 1.0
+    lam: float = 1.0
+    tau: float = float(1.0 / np.sqrt(12.0))
+    sigma: float = float(1.0 / np.sqrt(12.0))
+    iters: int = 300
+    storage: int = STORE_F32
+    schedule: int = SCHED_FUSED
+
+    def to_c(self) -> ParamsT:
+        p = ParamsT()
+        p.alpha0, p.alpha1, p.lam = self.alpha0, self.alpha1, self.lam
+        p.tau, p.sigma = self.tau, self.sigma
+        p.iters, p.storage, p.schedule = int(self.iters), int(self.storage), int(self.schedule)
+        return p
+
+
+def grid_c(origin, h, n, halo=0) -> GridT:
+    g = GridT()
+    for i in range(3):
+        g.origin[i] = float(origin[i])
+    g.h = float(h)
+    g.nx, g.ny, g.nz = (int(v) for v in n)
+    g.halo = int(halo)
+    return g
+
+
+def grid_from(obj) -> GridT:
+    """Accepts a GridT or any object with origin, h, n, halo attributes."""
+    if isinstance(obj, GridT):
+        return obj
+    return grid_c(obj.origin, obj.h, obj.n, getattr(obj, "halo", 0))
+
+
+def cameras_c(R, t, intr, wh, vote):
+    n = int(np.asarray(R).shape[0])
+    arr = (Camera * max(n, 1))()
+    R = np.asarray(R, dtype=np.float32).reshape(n, 9)
+    t = np.asarray(t, dtype=np.float32).reshape(n, 3)
+    intr = np.asarray(intr, dtype=np.float32).reshape(n, 4)
+    wh = np.asarray(wh, dtype=np.int32).reshape(n, 2)
+    vote = np.asarray(vote, dtype=np.int32).reshape(n)
+    for k in range(n):
+        c = arr[k]
+        for i in range(9):
+            c.R[i] = float(R[k, i])
+        for i in range(3):
+            c.t[i] = float(t[k, i])
+        c.fx, c.fy, c.cx, c.cy = (float(v) for v in intr[k])
+        c.width, c.height = int(wh[k, 0]), int(wh[k, 1])
+        c.vote = int(vote[k])
+        c.reserved = 0
+    return arr, n
+
+
+def cameras_from(obj):
+    """Accepts (array, n) or an object with R, t, intr, wh, vote arrays."""
+    if isinstance(obj, tuple):
+        return obj
+    return cameras_c(obj.R, obj.t, obj.intr, obj.wh, obj.vote)
+
+
+def stats_dict(s: StatsT) -> dict:
+    return dict(primal=s.primal, dual=s.dual, gap_rel=s.gap_rel, parts=[s.parts[0], s.parts[1], s.parts[2]],
+                nonfinite=int(s.nonfinite), iters_done=int(s.iters_done))
+
+
+# ---------------------------------------------------------------------------
+# context and calls
+# ---------------------------------------------------------------------------
+class Context:
+    """A libtgv context on one device (owns the library-side workspace)."""
+
+    def __init__(self, device: int = None):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libtgv needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = _vp()
+        st = self.lib.tgv_create(self.device, ctypes.byref(h))
+        if st != TGV_OK:
+            raise TgvError(st, f"tgv_create(device={self.device}) failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tgv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != TGV_OK:
+            msg = self.lib.tgv_last_error(self.h)
+            raise TgvError(st, msg.decode() if msg else "")
+
+    # -- pyramids ----------------------------------------------------------
+    def pyramid_floats(self, W: int, H: int) -> int:
+        return int(self.lib.tgv_pyramid_floats(W, H))
+
+    def pyramid_levels(self, W: int, H: int) -> int:
+        return int(self.lib.tgv_pyramid_levels(W, H))
+
+    def build_pyramids(self, depth: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        n, H, W = depth.shape
+        if depth.dtype != torch.float32:
+            raise ValueError("depth maps must be float32")
+        if out is None:
+            out = torch.empty((n, self.pyramid_floats(W, H)), dtype=torch.float32, device=depth.device)
+        self._check(self.lib.tgv_build_pyramids(self.h, _ptr(depth), n, W, H, _ptr(out), _stream(stream)))
+        return out
+
+    # -- histograms --------------------------------------------------------
+    def cull(self, cams, grid) -> np.ndarray:
+        arr, n = cameras_from(cams)
+        keep = (ctypes.c_int32 * max(n, 1))()
+        g = grid_from(grid)
+        cnt = self.lib.tgv_cull_cameras(arr, n, ctypes.byref(g), keep)
+        if cnt < 0:
+            raise TgvError(TGV_E_INVAL, "tgv_cull_cameras: bad arguments")
+        return np.array(keep[:cnt], dtype=np.int32)
+
+    def build_histograms(self, pyr: torch.Tensor, W: int, H: int, cams, grid, bins: Bins = None,
+                         out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """uint16 histograms as an int16 tensor [n_voxels, 8] (reinterpret as uint16)."""
+        g = grid_from(grid)
+        b = (bins or Bins()).to_c(g.h)
+        arr, n = cameras_from(cams)
+        nvox = g.nx * g.ny * g.nz
+        if out is None:
+            out = torch.empty((nvox, 8), dtype=torch.int16, device=pyr.device)
+        self._check(self.lib.tgv_build_histograms(self.h, _ptr(pyr), W, H, arr, n, ctypes.byref(g), ctypes.byref(b),
+                                                  _ptr(out), _stream(stream)))
+        return out
+
+    # -- solver ------------------------------------------------------------
+    def state(self, grid, storage: int = STORE_F32) -> "State":
+        return State(self, grid, storage)
+
+    def solve(self, grid, hist: torch.Tensor, u_io: torch.Tensor, params: Params = None, bins: Bins = None,
+              state: "State" = None, stats: bool = False, stream=None):
+        """Run params.iters iterations; fresh from u_io unless a state is given.
+        Returns the stats dict when stats=True (synchronises), else None."""
+        g = grid_from(grid)
+        p = (params or Params()).to_c()
+        b = (bins or Bins()).to_c(g.h)
+        s = StatsT()
+        self._check(self.lib.tgv_solve(self.h, ctypes.byref(g), _ptr(hist), ctypes.byref(b), ctypes.byref(p),
+                                       _ptr(u_io), state.h if state is not None else None,
+                                       ctypes.byref(s) if stats else None, _stream(stream)))
+        return stats_dict(s) if stats else None
+
+    def energy(self, state: "State", hist: torch.Tensor, params: Params = None, bins: Bins = None,
+               stream=None) -> dict:
+        p = (params or Params()).to_c()
+        b = (bins or Bins()).to_c(state.grid.h)
+        s = StatsT()
+        self._check(self.lib.tgv_energy(self.h, state.h, _ptr(hist), ctypes.byref(b), ctypes.byref(p),
+                                        ctypes.byref(s), _stream(stream)))
+        return stats_dict(s)
+
+
+class State:
+    """A resumable solver state (device memory owned by libtgv)."""
+
+    def __init__(self, ctx: Context, grid, storage: int = STORE_F32):
+        self.ctx = ctx
+        self.grid = grid_from(grid)
+        self.storage = storage
+        h = _vp()
+        ctx._check(ctx.lib.tgv_state_create(ctx.h, ctypes.byref(self.grid), storage, ctypes.byref(h)))
+        self.h = h
+        self.n = self.grid.nx * self.grid.ny * self.grid.nz
+
+    def bytes(self) -> int:
+        return int(self.ctx.lib.tgv_state_bytes(ctypes.byref(self.grid), self.storage))
+
+    def reset(self, u0: torch.Tensor, stream=None):
+        self.ctx._check(self.ctx.lib.tgv_state_reset(self.ctx.h, self.h, _ptr(u0), _stream(stream)))
+
+    def export(self, stream=None) -> dict:
+        dev = torch.device("cuda", self.ctx.device)
+        n = self.n
+        out = dict(u=torch.empty(n, device=dev), v=torch.empty(3 * n, device=dev),
+                   u_prev=torch.empty(n, device=dev), v_prev=torch.empty(3 * n, device=dev),
+                   p=torch.empty(3 * n, device=dev), q=torch.empty(6 * n, device=dev))
+        self.ctx._check(self.ctx.lib.tgv_state_export(self.ctx.h, self.h, _ptr(out["u"]), _ptr(out["v"]),
+                                                      _ptr(out["u_prev"]), _ptr(out["v_prev"]), _ptr(out["p"]),
+                                                      _ptr(out["q"]), _stream(stream)))
+        return out
+
+    def import_(self, f: dict, iters_done: int = 0, stream=None):
+        self.ctx._check(self.ctx.lib.tgv_state_import(self.ctx.h, self.h, _ptr(f["u"]), _ptr(f["v"]),
+                                                      _ptr(f["u_prev"]), _ptr(f["v_prev"]), _ptr(f["p"]),
+                                                      _ptr(f["q"]), int(iters_done), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tgv_state_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,526 @@
+// C ABI of libtgv: argument checking, camera culling, workspace and state
+// management, and the launch sequence of a solve.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+using namespace tgv;
+
+namespace {
+
+tgv_status fail(tgv_ctx *ctx, tgv_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+#define HIP_TRY(ctx, call)                                                                           \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? TGV_E_NOMEM : TGV_E_DEVICE, "%s: %s", #call, \
+                        hipGetErrorString(e_));                                                      \
+    } while (0)
+
+tgv_status check_launch(tgv_ctx *ctx, const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, TGV_E_DEVICE, "%s launch: %s", what, hipGetErrorString(e));
+    return TGV_OK;
+}
+
+bool grid_ok(const tgv_grid *g) {
+    if (!g) return false;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->halo < 0) return false;
+    int m = std::min(g->nx, std::min(g->ny, g->nz));
+    if (2LL * g->halo >= m) return false;
+    if (!(g->h > 0.0f) || !isfinite(g->h)) return false;
+    for (int i = 0; i < 3; i++)
+        if (!isfinite(g->origin[i])) return false;
+    long long n = (long long)g->nx * g->ny * g->nz;
+    return n <= (1LL << 31) / 8;  // q offsets (6 n) stay far inside 32-bit element counts
+}
+
+bool bins_ok(const tgv_bins *b) {
+    if (!b || b->num_bins < 1 || b->num_bins > 8) return false;
+    if (b->rule != 0 && b->rule != 1) return false;
+    if (!(b->delta > 0.0f) || !isfinite(b->delta)) return false;
+    if (!(b->eta_over_delta >= 0.0f) || !isfinite(b->eta_over_delta)) return false;
+    for (int k = 0; k < b->num_bins; k++) {
+        if (!isfinite(b->centers[k])) return false;
+        if (k > 0 && !(b->centers[k] > b->centers[k - 1])) return false;
+    }
+    return true;
+}
+
+bool params_ok(const tgv_params *p) {
+    if (!p) return false;
+    if (!(p->tau > 0.0f) || !(p->sigma > 0.0f) || !isfinite(p->tau) || !isfinite(p->sigma)) return false;
+    if (!(p->alpha0 >= 0.0f) || !(p->alpha1 >= 0.0f) || !(p->lambda >= 0.0f)) return false;
+    if (!isfinite(p->alpha0) || !isfinite(p->alpha1) || !isfinite(p->lambda)) return false;
+    if (p->iters < 0) return false;
+    if (p->storage < 0 || p->storage > 2) return false;
+    if (p->schedule != TGV_SCHED_FUSED && p->schedule != TGV_SCHED_SPLIT) return false;
+    return true;
+}
+
+Dims make_dims(const tgv_grid &g) {
+    Dims d;
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.nz = g.nz;
+    d.halo = g.halo;
+    d.sy = g.nx;
+    d.sz = (long long)g.nx * g.ny;
+    d.n = d.sz * g.nz;
+    return d;
+}
+
+Coef make_coef(const tgv_params &p, const tgv_bins &b) {
+    Coef c;
+    c.alpha0 = p.alpha0;
+    c.alpha1 = p.alpha1;
+    c.tau = p.tau;
+    c.sigma = p.sigma;
+    c.taulam = p.tau * p.lambda;
+    for (int k = 0; k < 8; k++) c.c[k] = k < b.num_bins ? b.centers[k] : INFINITY;
+    return c;
+}
+
+long long align256(long long x) { return (x + 255) & ~255LL; }
+
+SolveBufs bufs_of(const tgv_state *st, int xc, int yc, const uint16_t *hist) {
+    SolveBufs b;
+    b.xc_u = st->u[xc];
+    b.xc_v = st->v[xc];
+    b.xo_u = st->u[xc ^ 1];
+    b.xo_v = st->v[xc ^ 1];
+    b.yc_p = st->p[yc];
+    b.yc_q = st->q[yc];
+    b.yo_p = st->p[yc ^ 1];
+    b.yo_q = st->q[yc ^ 1];
+    b.hist = hist;
+    return b;
+}
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+// ===========================================================================
+// context
+// ===========================================================================
+extern "C" tgv_status tgv_create(int device, tgv_ctx **out) {
+    if (!out) return TGV_E_INVAL;
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return TGV_E_DEVICE;
+    tgv_ctx *c = new tgv_ctx();
+    c->device = device;
+    c->cams_host = nullptr;
+    c->cams_dev = nullptr;
+    c->cams_cap = 0;
+    c->partials = nullptr;
+    c->partials_cap = 0;
+    c->eout_dev = nullptr;
+    c->eout_host = nullptr;
+    c->own = nullptr;
+    if (hipEventCreateWithFlags(&c->cams_evt, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc((void **)&c->eout_dev, sizeof(EnergyOut)) != hipSuccess ||
+        hipHostMalloc((void **)&c->eout_host, sizeof(EnergyOut), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return TGV_E_DEVICE;
+    }
+    *out = c;
+    return TGV_OK;
+}
+
+extern "C" void tgv_destroy(tgv_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->own) tgv_state_destroy(c->own);
+    (void)hipFree(c->cams_dev);
+    (void)hipHostFree(c->cams_host);
+    (void)hipFree(c->partials);
+    (void)hipFree(c->eout_dev);
+    (void)hipHostFree(c->eout_host);
+    (void)hipEventDestroy(c->cams_evt);
+    delete c;
+}
+
+extern "C" const char *tgv_last_error(const tgv_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+// ===========================================================================
+// pyramids
+// ===========================================================================
+extern "C" int32_t tgv_pyramid_levels(int32_t W, int32_t H) {
+    if (W < 1 || H < 1) return 0;
+    return pyr_geom(W, H).L;
+}
+
+extern "C" int64_t tgv_pyramid_floats(int32_t W, int32_t H) {
+    if (W < 1 || H < 1) return 0;
+    return pyr_geom(W, H).cam_stride;
+}
+
+extern "C" tgv_status tgv_build_pyramids(tgv_ctx *ctx, const float *depth, int32_t n_cams, int32_t W, int32_t H,
+                                         float *pyr, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!depth || !pyr || n_cams < 1 || W < 1 || H < 1 || n_cams > 65535)
+        return fail(ctx, TGV_E_INVAL, "tgv_build_pyramids: bad arguments");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    PyrGeom g = pyr_geom(W, H);
+    if (g.L > 24) return fail(ctx, TGV_E_INVAL, "tgv_build_pyramids: image too large");
+    launch_pyramids(depth, n_cams, g, pyr, S(stream));
+    return check_launch(ctx, "pyramids");
+}
+
+// ===========================================================================
+// camera cull and histograms
+// ===========================================================================
+extern "C" int32_t tgv_cull_cameras(const tgv_camera *cams, int32_t n_cams, const tgv_grid *grid, int32_t *keep) {
+    if (!cams || !keep || n_cams < 0 || !grid_ok(grid)) return -1;
+    // bounding box of the voxel centres
+    double lo[3], hi[3];
+    int nn[3] = {grid->nx, grid->ny, grid->nz};
+    for (int i = 0; i < 3; i++) {
+        lo[i] = (double)grid->origin[i] + 0.5 * grid->h;
+        hi[i] = (double)grid->origin[i] + (nn[i] - 0.5) * (double)grid->h;
+    }
+    int cnt = 0;
+    for (int c = 0; c < n_cams; c++) {
+        const tgv_camera &cm = cams[c];
+        double zmin = INFINITY, pxmin = INFINITY, pxmax = -INFINITY, pymin = INFINITY, pymax = -INFINITY;
+        bool all_front = true;
+        for (int k = 0; k < 8; k++) {
+            double P[3] = {(k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2]};
+            double xc[3];
+            for (int r = 0; r < 3; r++)
+                xc[r] = cm.R[3 * r] * P[0] + cm.R[3 * r + 1] * P[1] + cm.R[3 * r + 2] * P[2] + cm.t[r];
+            zmin = std::min(zmin, xc[2]);
+            if (xc[2] <= 0.0) {
+                all_front = false;
+                continue;
+            }
+            double px = cm.fx * (xc[0] / xc[2]) + cm.cx, py = cm.fy * (xc[1] / xc[2]) + cm.cy;
+            pxmin = std::min(pxmin, px);
+            pxmax = std::max(pxmax, px);
+            pymin = std::min(pymin, py);
+            pymax = std::max(pymax, py);
+        }
+        double zmax_all = -INFINITY;
+        for (int k = 0; k < 8; k++) {
+            double P[3] = {(k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2]};
+            double z = cm.R[6] * P[0] + cm.R[7] * P[1] + cm.R[8] * P[2] + cm.t[2];
+            zmax_all = std::max(zmax_all, z);
+        }
+        // every voxel centre is a convex combination of the corners: if all
+        // corners are behind the camera (with a float32 rounding margin), so
+        // is every centre
+        double zscale = 1e-5 * (fabs(cm.t[2]) + fabs(hi[0]) + fabs(hi[1]) + fabs(hi[2]) + fabs(lo[0]) + fabs(lo[1]) +
+                                fabs(lo[2]) + 1.0);
+        if (zmax_all < -zscale) continue;
+        if (all_front && zmin > zscale) {
+            // projections of centres lie in the convex hull of the corner
+            // projections; keep a 2-pixel (+ relative) margin for rounding
+            double mx = 2.0 + 1e-5 * (fabs(pxmin) + fabs(pxmax));
+            double my = 2.0 + 1e-5 * (fabs(pymin) + fabs(pymax));
+            if (pxmax < -mx || pxmin > cm.width + mx || pymax < -my || pymin > cm.height + my) continue;
+        }
+        keep[cnt++] = c;
+    }
+    return cnt;
+}
+
+extern "C" tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32_t W, int32_t H,
+                                           const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid,
+                                           const tgv_bins *bins, uint16_t *hist, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!pyr || !hist || !cams_host || n_cams < 0 || W < 1 || H < 1)
+        return fail(ctx, TGV_E_INVAL, "tgv_build_histograms: bad arguments");
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_build_histograms: bad grid");
+    if (!bins_ok(bins)) return fail(ctx, TGV_E_INVAL, "tgv_build_histograms: bad bins");
+    for (int c = 0; c < n_cams; c++) {
+        if (cams_host[c].width != W || cams_host[c].height != H)
+            return fail(ctx, TGV_E_INVAL, "camera %d is %dx%d, pyramids are %dx%d", c, cams_host[c].width,
+                        cams_host[c].height, W, H);
+        if (cams_host[c].vote < 0 || cams_host[c].vote > 65535)
+            return fail(ctx, TGV_E_INVAL, "camera %d has vote %d", c, cams_host[c].vote);
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    std::vector<int32_t> keep(n_cams > 0 ? n_cams : 1);
+    int nk = tgv_cull_cameras(cams_host, n_cams, grid, keep.data());
+    long long total = 0;
+    for (int k = 0; k < nk; k++) total += cams_host[keep[k]].vote;
+    if (total > 65535)
+        return fail(ctx, TGV_E_OVERFLOW, "votes of %d cameras sum to %lld > 65535", nk, total);
+    // stage the culled camera table (wait until the previous upload left the staging buffer)
+    HIP_TRY(ctx, hipEventSynchronize(ctx->cams_evt));
+    if (nk > ctx->cams_cap) {
+        int cap = std::max(nk, 64);
+        (void)hipFree(ctx->cams_dev);
+        (void)hipHostFree(ctx->cams_host);
+        ctx->cams_dev = nullptr;
+        ctx->cams_host = nullptr;
+        ctx->cams_cap = 0;
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->cams_dev, sizeof(CamDev) * cap));
+        HIP_TRY(ctx, hipHostMalloc((void **)&ctx->cams_host, sizeof(CamDev) * cap, hipHostMallocDefault));
+        ctx->cams_cap = cap;
+    }
+    for (int k = 0; k < nk; k++) {
+        const tgv_camera &c = cams_host[keep[k]];
+        CamDev &d = ctx->cams_host[k];
+        memcpy(d.R, c.R, sizeof(d.R));
+        memcpy(d.t, c.t, sizeof(d.t));
+        d.fx = c.fx;
+        d.fy = c.fy;
+        d.cx = c.cx;
+        d.cy = c.cy;
+        d.vote = c.vote;
+        d.pyr = keep[k];
+        d.pad[0] = d.pad[1] = 0;
+    }
+    if (nk > 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->cams_dev, ctx->cams_host, sizeof(CamDev) * nk, hipMemcpyHostToDevice,
+                                    S(stream)));
+        HIP_TRY(ctx, hipEventRecord(ctx->cams_evt, S(stream)));
+    }
+    PyrGeom g = pyr_geom(W, H);
+    if (g.L > 24) return fail(ctx, TGV_E_INVAL, "image too large");
+    launch_histograms(pyr, g, ctx->cams_dev, nk, *grid, *bins, hist, S(stream));
+    return check_launch(ctx, "histograms");
+}
+
+// ===========================================================================
+// solver state
+// ===========================================================================
+extern "C" int64_t tgv_state_bytes(const tgv_grid *grid, int32_t storage) {
+    if (!grid_ok(grid) || storage < 0 || storage > 2) return -1;
+    long long n = (long long)grid->nx * grid->ny * grid->nz;
+    long long sb = storage_bytes(storage);
+    return 2 * align256(4 * n) + 2 * align256(3 * n * sb) + 2 * align256(3 * n * sb) + 2 * align256(6 * n * sb);
+}
+
+extern "C" tgv_status tgv_state_create(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, tgv_state **out) {
+    if (!ctx || !out) return TGV_E_INVAL;
+    *out = nullptr;
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_state_create: bad grid");
+    if (storage < 0 || storage > 2) return fail(ctx, TGV_E_INVAL, "tgv_state_create: bad storage %d", storage);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    tgv_state *st = new tgv_state();
+    st->grid = *grid;
+    st->storage = storage;
+    st->n = (long long)grid->nx * grid->ny * grid->nz;
+    long long bytes = tgv_state_bytes(grid, storage);
+    if (hipMalloc(&st->mem, bytes) != hipSuccess) {
+        delete st;
+        (void)hipGetLastError();
+        return fail(ctx, TGV_E_NOMEM, "tgv_state_create: cannot allocate %lld bytes", bytes);
+    }
+    long long sb = storage_bytes(storage), n = st->n;
+    char *b = (char *)st->mem;
+    for (int k = 0; k < 2; k++) {
+        st->u[k] = (float *)b;
+        b += align256(4 * n);
+    }
+    for (int k = 0; k < 2; k++) {
+        st->v[k] = b;
+        b += align256(3 * n * sb);
+    }
+    for (int k = 0; k < 2; k++) {
+        st->p[k] = b;
+        b += align256(3 * n * sb);
+    }
+    for (int k = 0; k < 2; k++) {
+        st->q[k] = b;
+        b += align256(6 * n * sb);
+    }
+    st->xc = 0;
+    st->yc = 0;
+    st->fresh = true;
+    st->iters_done = 0;
+    *out = st;
+    return TGV_OK;
+}
+
+extern "C" void tgv_state_destroy(tgv_state *st) {
+    if (!st) return;
+    (void)hipFree(st->mem);
+    delete st;
+}
+
+extern "C" tgv_status tgv_state_reset(tgv_ctx *ctx, tgv_state *st, const float *u0, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!st || !u0) return fail(ctx, TGV_E_INVAL, "tgv_state_reset: null argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    long long n = st->n, sb = storage_bytes(st->storage);
+    st->xc = 0;
+    st->yc = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(st->u[0], u0, 4 * n, hipMemcpyDeviceToDevice, S(stream)));
+    launch_fill_bytes0(st->v[0], 3 * n * sb, S(stream));
+    launch_fill_bytes0(st->p[0], 3 * n * sb, S(stream));
+    launch_fill_bytes0(st->q[0], 6 * n * sb, S(stream));
+    st->fresh = true;
+    st->iters_done = 0;
+    return check_launch(ctx, "state reset");
+}
+
+extern "C" tgv_status tgv_state_export(tgv_ctx *ctx, const tgv_state *st, float *u, float *v, float *u_prev,
+                                       float *v_prev, float *p, float *q, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!st) return fail(ctx, TGV_E_INVAL, "tgv_state_export: null state");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    long long n = st->n;
+    int xp = st->fresh ? st->xc : (st->xc ^ 1);
+    if (u) HIP_TRY(ctx, hipMemcpyAsync(u, st->u[st->xc], 4 * n, hipMemcpyDeviceToDevice, S(stream)));
+    if (u_prev) HIP_TRY(ctx, hipMemcpyAsync(u_prev, st->u[xp], 4 * n, hipMemcpyDeviceToDevice, S(stream)));
+    if (v) launch_convert(st->v[st->xc], st->storage, v, 0, 3 * n, S(stream));
+    if (v_prev) launch_convert(st->v[xp], st->storage, v_prev, 0, 3 * n, S(stream));
+    if (p) launch_convert(st->p[st->yc], st->storage, p, 0, 3 * n, S(stream));
+    if (q) launch_convert(st->q[st->yc], st->storage, q, 0, 6 * n, S(stream));
+    return check_launch(ctx, "state export");
+}
+
+extern "C" tgv_status tgv_state_import(tgv_ctx *ctx, tgv_state *st, const float *u, const float *v,
+                                       const float *u_prev, const float *v_prev, const float *p, const float *q,
+                                       int64_t iters_done, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!st || !u || !v || !u_prev || !v_prev || !p || !q)
+        return fail(ctx, TGV_E_INVAL, "tgv_state_import: null argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    long long n = st->n;
+    st->xc = 0;
+    st->yc = 0;
+    st->fresh = false;
+    HIP_TRY(ctx, hipMemcpyAsync(st->u[0], u, 4 * n, hipMemcpyDeviceToDevice, S(stream)));
+    HIP_TRY(ctx, hipMemcpyAsync(st->u[1], u_prev, 4 * n, hipMemcpyDeviceToDevice, S(stream)));
+    launch_convert(v, 0, st->v[0], st->storage, 3 * n, S(stream));
+    launch_convert(v_prev, 0, st->v[1], st->storage, 3 * n, S(stream));
+    launch_convert(p, 0, st->p[0], st->storage, 3 * n, S(stream));
+    launch_convert(q, 0, st->q[0], st->storage, 6 * n, S(stream));
+    st->iters_done = iters_done;
+    return check_launch(ctx, "state import");
+}
+
+// ===========================================================================
+// solve
+// ===========================================================================
+static bool same_grid(const tgv_grid &a, const tgv_grid &b) {
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.halo == b.halo;
+}
+
+static tgv_status run_energy(tgv_ctx *ctx, const tgv_state *st, const uint16_t *hist, const tgv_bins *bins,
+                             const tgv_params *params, tgv_stats *out, hipStream_t s) {
+    Dims d = make_dims(st->grid);
+    Coef cf = make_coef(*params, *bins);
+    int np = energy_partials(d);
+    if (np > ctx->partials_cap) {
+        (void)hipFree(ctx->partials);
+        ctx->partials = nullptr;
+        ctx->partials_cap = 0;
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->partials, sizeof(double) * 5 * np));
+        ctx->partials_cap = np;
+    }
+    SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
+    launch_energy(st->storage, b, d, cf, params->lambda, 2.0 * sqrt(3.0), ctx->partials, np, ctx->eout_dev, s);
+    tgv_status r = check_launch(ctx, "energy");
+    if (r != TGV_OK) return r;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->eout_host, ctx->eout_dev, sizeof(EnergyOut), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const EnergyOut &e = *ctx->eout_host;
+    out->parts[0] = e.part[0];
+    out->parts[1] = e.part[1];
+    out->parts[2] = e.part[2];
+    out->primal = e.part[0] + e.part[1] + e.part[2];
+    out->dual = e.dual;
+    out->gap_rel = (out->primal - out->dual) / std::max(out->primal, 1.0);
+    out->nonfinite = (int64_t)e.nonfinite;
+    out->iters_done = st->iters_done;
+    return TGV_OK;
+}
+
+extern "C" tgv_status tgv_energy(tgv_ctx *ctx, const tgv_state *st, const uint16_t *hist, const tgv_bins *bins,
+                                 const tgv_params *params, tgv_stats *stats_host, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!st || !hist || !stats_host) return fail(ctx, TGV_E_INVAL, "tgv_energy: null argument");
+    if (!bins_ok(bins) || !params_ok(params)) return fail(ctx, TGV_E_INVAL, "tgv_energy: bad bins or params");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return run_energy(ctx, st, hist, bins, params, stats_host, S(stream));
+}
+
+extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
+                                const tgv_params *params, float *u_io, tgv_state *state, tgv_stats *stats_host,
+                                void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad grid");
+    if (!bins_ok(bins)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad bins");
+    if (!params_ok(params)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad params");
+    if (!hist) return fail(ctx, TGV_E_INVAL, "tgv_solve: null hist");
+    if (!state && !u_io) return fail(ctx, TGV_E_INVAL, "tgv_solve: fresh solve needs u_io");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = S(stream);
+    tgv_state *st = state;
+    if (st) {
+        if (!same_grid(st->grid, *grid) || st->storage != params->storage)
+            return fail(ctx, TGV_E_INVAL, "tgv_solve: state does not match grid/storage");
+    } else {
+        if (ctx->own && (!same_grid(ctx->own->grid, *grid) || ctx->own->storage != params->storage)) {
+            HIP_TRY(ctx, hipStreamSynchronize(s));
+            tgv_state_destroy(ctx->own);
+            ctx->own = nullptr;
+        }
+        if (!ctx->own) {
+            tgv_status r = tgv_state_create(ctx, grid, params->storage, &ctx->own);
+            if (r != TGV_OK) return r;
+        }
+        st = ctx->own;
+        st->grid = *grid;
+        tgv_status r = tgv_state_reset(ctx, st, u_io, stream);
+        if (r != TGV_OK) return r;
+    }
+    Dims d = make_dims(*grid);
+    Coef cf = make_coef(*params, *bins);
+    int N = params->iters;
+    if (N > 0) {
+        // dual step from (x^n, x^{n-1}, y^n): y^{n+1}, in place
+        {
+            SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
+            if (st->fresh) {
+                b.xo_u = b.xc_u;
+                b.xo_v = b.xc_v;
+            }
+            launch_ref(KIND_DUAL, st->storage, b, d, cf, s);
+        }
+        if (params->schedule == TGV_SCHED_SPLIT) {
+            for (int it = 0; it < N; it++) {
+                if (it > 0) launch_ref(KIND_DUAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
+                launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
+                st->xc ^= 1;
+            }
+        } else {
+            for (int it = 0; it + 1 < N; it++) {
+                launch_ref(KIND_FUSED, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
+                st->xc ^= 1;
+                st->yc ^= 1;
+            }
+            launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
+            st->xc ^= 1;
+        }
+        st->fresh = false;
+        st->iters_done += N;
+        tgv_status r = check_launch(ctx, "solve");
+        if (r != TGV_OK) return r;
+    }
+    if (u_io) HIP_TRY(ctx, hipMemcpyAsync(u_io, st->u[st->xc], 4 * st->n, hipMemcpyDeviceToDevice, s));
+    if (stats_host) return run_energy(ctx, st, hist, bins, params, stats_host, s);
+    return TGV_OK;
+}

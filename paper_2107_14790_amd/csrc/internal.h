@@ -1,0 +1,101 @@
+// Host-side internals of libtgv: context and state objects, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/tgv.h"
+#include "device_math.h"
+
+namespace tgv {
+
+enum { KIND_DUAL = 0, KIND_PRIMAL = 1, KIND_FUSED = 2 };
+
+// Raw pointers of one solver launch: the current iterate (xc, yc), the
+// other buffers (xo, yo) and the histograms.  v/p/q point at storage of
+// the state's precision.
+struct SolveBufs {
+    float *xc_u;
+    void *xc_v;
+    float *xo_u;
+    void *xo_v;
+    void *yc_p, *yc_q;
+    void *yo_p, *yo_q;
+    const uint16_t *hist;
+};
+
+// Geometry of a packed pyramid (all cameras the same size).
+struct PyrGeom {
+    int L;
+    int W, H;
+    long long cam_stride;
+    long long off[24];
+    int w[24], h[24];
+};
+
+// A camera as the histogram kernel reads it (uniform per loop trip).
+struct CamDev {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int vote;
+    int pyr;  // index of its pyramid in the packed buffer
+    int pad[2];
+};
+
+// Energy reduction output (device): primal parts (3), dual, nonfinite.
+struct EnergyOut {
+    double part[3];
+    double dual;
+    double nonfinite;
+};
+
+int64_t storage_bytes(int storage);
+
+void launch_ref(int kind, int storage, const SolveBufs &b, const Dims &d, const Coef &cf, hipStream_t s);
+void launch_energy(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, float lambda, double vbound,
+                   double *partials, int nparts, EnergyOut *out, hipStream_t s);
+int energy_partials(const Dims &d);
+void launch_pyramids(const float *depth, int ncam, const PyrGeom &g, float *pyr, hipStream_t s);
+void launch_histograms(const float *pyr, const PyrGeom &g, const CamDev *cams, int ncam, const tgv_grid &grid,
+                       const tgv_bins &bins, uint16_t *hist, hipStream_t s);
+void launch_fill(float *p, float v, long long n, hipStream_t s);
+void launch_fill_bytes0(void *p, long long nbytes, hipStream_t s);
+void launch_convert(const void *src, int src_storage, void *dst, int dst_storage, long long n, hipStream_t s);
+
+PyrGeom pyr_geom(int W, int H);
+
+}  // namespace tgv
+
+struct tgv_ctx {
+    int device;
+    std::string err;
+    // pinned staging for the camera table + its device copy
+    tgv::CamDev *cams_host;
+    tgv::CamDev *cams_dev;
+    int cams_cap;
+    hipEvent_t cams_evt;
+    // energy reduction scratch
+    double *partials;
+    int partials_cap;
+    tgv::EnergyOut *eout_dev;
+    tgv::EnergyOut *eout_host;
+    // state used by tgv_solve when the caller passes none
+    tgv_state *own;
+};
+
+struct tgv_state {
+    tgv_grid grid;
+    int storage;
+    void *mem;              // one allocation holding every field
+    long long n;
+    float *u[2];
+    void *v[2];
+    void *p[2];
+    void *q[2];
+    int xc, yc;             // current primal and dual buffer
+    bool fresh;             // previous iterate == current (no step taken yet)
+    int64_t iters_done;
+};

@@ -336,7 +336,7 @@ def heightfield_depth(cams: Cameras, k: int, hf: HeightField, bisect: int = 10, 
 def terrain_scene(seed: int = 2, n: int = 256, n_side: int = 8, W: int = 1024, H: int = 1024,
                   f: float = 1536.0, altitude: float = 1.5, lattice: int = 2048, hurst: float = 0.8,
                   amplitude: float = 0.2, sigma_vox: float = 0.3, outlier_frac: float = 0.01,
-                  origin=(0.0, 0.0, 0.0), extent: float = 1.0) -> Scene:
+                  origin=(0.0, 0.0, 0.0), extent: float = 1.0, device: str = "cpu") -> Scene:
     """fBm terrain (peak-to-peak `amplitude`, centred at mid-height of the
     unit cube) under an n_side x n_side grid of nadir cameras at `altitude`
     above mid-height; the block is n^3 voxels over [0, extent]^3 + origin."""
@@ -352,7 +352,7 @@ def terrain_scene(seed: int = 2, n: int = 256, n_side: int = 8, W: int = 1024, H
     cams = make_cameras(Rs, ts, f, f, W / 2.0, H / 2.0, W, H)
     h = float(np.float32(extent / n))
     grid = Grid(np.asarray(origin, dtype=np.float32), h, (n, n, n), 0)
-    clean = np.stack([heightfield_depth(cams, k, hf) for k in range(len(cams))])
+    clean = np.stack([heightfield_depth(cams, k, hf, device=device) for k in range(len(cams))])
     rng = np.random.default_rng(seed + 1000)
     depth = add_noise(clean, cams, grid, sigma_vox * h, outlier_frac, rng)
     return Scene(depth, cams, grid, name=f"terrain{n}")

@@ -1,0 +1,287 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.  Histograms and pyramids bit-exact; u within 1e-4
+max-abs of the float64 oracle; energies within float64 reduction error."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+TAU = float(np.float32(1.0 / np.sqrt(12.0)))
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2107_14790_amd as tgv
+    return tgv.Context(0)
+
+
+def gpu_hist(ctx, sc, rule=0, num_bins=7):
+    import paper_2107_14790_amd as tgv
+    d = torch.from_numpy(sc.depth).cuda()
+    H, W = sc.depth.shape[1:]
+    pyr = ctx.build_pyramids(d)
+    hist = ctx.build_histograms(pyr, W, H, sc.cams, sc.grid, tgv.Bins(num_bins=num_bins, rule=rule))
+    torch.cuda.synchronize()
+    return pyr.cpu().numpy(), hist.cpu().numpy().view(np.uint16)
+
+
+# ---------------------------------------------------------------------------
+# pyramids and histograms: bit-exact
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("W,H", [(128, 128), (100, 75), (7, 3), (1, 1), (513, 257)])
+def test_pyramids_bit_exact(ctx, W, H):
+    say("pyramids", W, H)
+    rng = np.random.default_rng(W * 1000 + H)
+    d = rng.uniform(0.5, 3.0, size=(3, H, W)).astype(np.float32)
+    d[rng.random(d.shape) < 0.2] = 0.0
+    d[rng.random(d.shape) < 0.05] = np.nan
+    d[rng.random(d.shape) < 0.05] = -1.0
+    d[rng.random(d.shape) < 0.02] = np.inf
+    pyr = ctx.build_pyramids(torch.from_numpy(d).cuda()).cpu().numpy()
+    for c in range(3):
+        ref = oracle.pyramid(d[c])
+        assert np.array_equal(pyr[c].view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_sphere_histograms_bit_exact(ctx, rule):
+    say("sphere32 histograms rule", rule)
+    sc = scenes.sphere_scene()
+    pyr, hist = gpu_hist(ctx, sc, rule=rule)
+    ref_pyr = oracle.pyramids(sc.depth)
+    assert np.array_equal(pyr.reshape(-1).view(np.uint32), ref_pyr.view(np.uint32))
+    ref, _ = oracle.histograms(sc, ref_pyr, rule=rule)
+    assert np.array_equal(hist, ref)
+    assert hist.sum() > 0
+
+
+@pytest.mark.parametrize("num_bins", [1, 2, 5, 8])
+def test_histograms_other_bin_counts(ctx, num_bins):
+    say("sphere16 histograms bins", num_bins)
+    sc = scenes.sphere_scene(n=16)
+    for rule in (0, 1):
+        _, hist = gpu_hist(ctx, sc, rule=rule, num_bins=num_bins)
+        ref, _ = oracle.histograms(sc, rule=rule, num_bins=num_bins)
+        assert np.array_equal(hist, ref)
+
+
+def test_ragged_terrain_histograms_bit_exact(ctx):
+    # several 64x4 tiles plus ragged tails in x and y, mip levels > 0
+    say("terrain ragged histograms")
+    sc = scenes.terrain_scene(n=40, n_side=3, W=160, H=144, f=200.0, lattice=256)
+    sc.grid.n = (70, 37, 23)
+    pyr, hist = gpu_hist(ctx, sc)
+    ref, _ = oracle.histograms(sc)
+    assert np.array_equal(hist, ref)
+
+
+def test_votes_weights_and_plane(ctx):
+    say("plane histograms with vote weights")
+    sc = scenes.plane_scene(n=(5, 4, 28), z_plane_index=12, n_cams=4)
+    sc.cams.vote[:] = [1, 5, 3, 5]
+    _, hist = gpu_hist(ctx, sc)
+    ref, _ = oracle.histograms(sc)
+    assert np.array_equal(hist, ref)
+
+
+def test_histogram_overflow_and_bad_args(ctx):
+    import paper_2107_14790_amd as tgv
+    say("histogram overflow error")
+    sc = scenes.plane_scene(n=(2, 2, 3), z_plane_index=1, n_cams=2)
+    sc.cams.vote[:] = [40000, 40000]
+    d = torch.from_numpy(sc.depth).cuda()
+    pyr = ctx.build_pyramids(d)
+    with pytest.raises(tgv.TgvError) as e:
+        ctx.build_histograms(pyr, 64, 64, sc.cams, sc.grid)
+    assert e.value.status == tgv.TGV_E_OVERFLOW
+    with pytest.raises(tgv.TgvError) as e:
+        ctx.build_histograms(pyr, 64, 64, sc.cams, sc.grid, tgv.Bins(num_bins=9))
+    assert e.value.status == tgv.TGV_E_INVAL
+    with pytest.raises(tgv.TgvError) as e:
+        ctx.build_histograms(pyr, 32, 64, sc.cams, sc.grid)  # camera size mismatch
+    assert e.value.status == tgv.TGV_E_INVAL
+
+
+# ---------------------------------------------------------------------------
+# solver
+# ---------------------------------------------------------------------------
+def solve_gpu(ctx, hist_np, shape, iters, halo=0, u0=None, storage=0, schedule=0, alpha0=2.0, alpha1=1.0,
+              lam=1.0, tau=TAU, stats=False):
+    import paper_2107_14790_amd as tgv
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    g = tgv.grid_c((0, 0, 0), 1.0, shape, halo)
+    hist = torch.from_numpy(hist_np.view(np.int16).reshape(n, 8)).cuda()
+    u = torch.zeros(n, device="cuda") if u0 is None else torch.from_numpy(np.asarray(u0, np.float32)).cuda()
+    p = tgv.Params(alpha0=alpha0, alpha1=alpha1, lam=lam, tau=tau, sigma=tau, iters=iters, storage=storage,
+                   schedule=schedule)
+    st = ctx.solve(g, hist, u, p, stats=stats)
+    torch.cuda.synchronize()
+    return u.cpu().numpy().astype(np.float64), st
+
+
+def test_sphere32_u_matches_oracle(ctx):
+    say("sphere32 solve 300 iterations")
+    sc = scenes.sphere_scene()
+    ref_h, _ = oracle.histograms(sc)
+    _, hist = gpu_hist(ctx, sc)
+    assert np.array_equal(hist, ref_h)
+    u_gpu, stats = solve_gpu(ctx, hist, (32, 32, 32), 300, stats=True)
+    st = oracle.solve(ref_h, (32, 32, 32), scenes.default_bins(), 300)
+    err = np.abs(u_gpu - st.u).max()
+    say("sphere32 max|u_gpu - u_oracle| =", err)
+    assert err <= 1e-4
+    P, D, g = oracle.gap(ref_h, (32, 32, 32), scenes.default_bins(), st)
+    assert abs(stats["primal"] - P) <= 1e-4 * P
+    assert stats["nonfinite"] == 0 and stats["iters_done"] == 300
+
+
+@pytest.mark.parametrize("shape,halo,iters", [((37, 29, 23), 2, 120), ((70, 9, 5), 0, 200), ((1, 1, 1), 0, 10),
+                                              ((17, 1, 1), 0, 150), ((1, 13, 6), 0, 90), ((64, 8, 8), 3, 60)])
+def test_ragged_blocks_match_oracle(ctx, shape, halo, iters):
+    say("ragged solve", shape, halo, iters)
+    rng = np.random.default_rng(sum(shape) + halo)
+    n = int(np.prod(shape))
+    hist = np.zeros((n, 8), dtype=np.uint16)
+    tot = rng.integers(0, 12, size=n)
+    for x in range(n):
+        if tot[x]:
+            hist[x, :7] = np.bincount(rng.integers(0, 7, size=tot[x]), minlength=7)
+    u0 = np.where(rng.random(n) < 0.5, rng.uniform(-1, 1, n), 0.0).astype(np.float32)
+    u_gpu, _ = solve_gpu(ctx, hist, shape, iters, halo=halo, u0=u0)
+    st = oracle.solve(hist, shape, scenes.default_bins(), iters, halo=halo, u0=u0.astype(np.float64))
+    assert np.abs(u_gpu - st.u).max() <= 1e-4
+    if halo:
+        nx, ny, nz = shape
+        z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        fr = ((x < halo) | (y < halo) | (z < halo) | (x >= nx - halo) | (y >= ny - halo) | (z >= nz - halo)).ravel()
+        assert np.array_equal(u_gpu[fr], u0[fr].astype(np.float64))
+
+
+def test_fused_and_split_schedules_bit_identical(ctx):
+    say("fused vs split")
+    sc = scenes.sphere_scene(n=24)
+    _, hist = gpu_hist(ctx, sc)
+    a, _ = solve_gpu(ctx, hist, (24, 24, 24), 57, schedule=0)
+    b, _ = solve_gpu(ctx, hist, (24, 24, 24), 57, schedule=1)
+    assert np.array_equal(a, b)
+
+
+def test_resume_is_bitwise_and_export_import_roundtrip(ctx):
+    import paper_2107_14790_amd as tgv
+    say("resume / export / import")
+    sc = scenes.sphere_scene(n=20)
+    _, hist_np = gpu_hist(ctx, sc)
+    g = tgv.grid_from(sc.grid)
+    n = 20 ** 3
+    hist = torch.from_numpy(hist_np.view(np.int16)).cuda()
+    u0 = torch.zeros(n, device="cuda")
+    full = tgv.State(ctx, g)
+    full.reset(u0)
+    ctx.solve(g, hist, None, tgv.Params(iters=90), state=full)
+    part = tgv.State(ctx, g)
+    part.reset(u0)
+    ctx.solve(g, hist, None, tgv.Params(iters=40), state=part)
+    f = part.export()
+    other = tgv.State(ctx, g)
+    other.import_(f, iters_done=40)
+    ctx.solve(g, hist, None, tgv.Params(iters=50), state=other)
+    ctx.solve(g, hist, None, tgv.Params(iters=50), state=part)
+    a, b, c = full.export(), part.export(), other.export()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(a[k], c[k]), k
+
+
+def test_state_fields_match_oracle(ctx):
+    import paper_2107_14790_amd as tgv
+    say("state fields vs oracle")
+    sc = scenes.sphere_scene(n=16)
+    ref_h, _ = oracle.histograms(sc)
+    g = tgv.grid_from(sc.grid)
+    hist = torch.from_numpy(ref_h.view(np.int16)).cuda()
+    st = tgv.State(ctx, g)
+    st.reset(torch.zeros(16 ** 3, device="cuda"))
+    ctx.solve(g, hist, None, tgv.Params(iters=100), state=st)
+    f = {k: v.cpu().numpy().astype(np.float64) for k, v in st.export().items()}
+    ref = oracle.solve(ref_h, (16, 16, 16), scenes.default_bins(), 100)
+    for k in ("u", "v", "p", "q"):
+        assert np.abs(f[k] - getattr(ref, k)).max() <= 1e-4, k
+    # ubar = 2 u - u_prev
+    assert np.abs((2 * f["u"] - f["u_prev"]) - ref.ubar).max() <= 2e-4
+
+
+def test_energy_reduction_matches_oracle_on_same_fields(ctx):
+    import paper_2107_14790_amd as tgv
+    say("energy parity")
+    sc = scenes.sphere_scene(n=24)
+    ref_h, _ = oracle.histograms(sc)
+    g = tgv.grid_c(sc.grid.origin, sc.grid.h, (24, 24, 24), 2)
+    hist = torch.from_numpy(ref_h.view(np.int16)).cuda()
+    st = tgv.State(ctx, g)
+    st.reset(torch.zeros(24 ** 3, device="cuda"))
+    ctx.solve(g, hist, None, tgv.Params(iters=80), state=st)
+    s = ctx.energy(st, hist)
+    f = {k: v.cpu().numpy().astype(np.float64) for k, v in st.export().items()}
+    c = scenes.default_bins()
+    P, parts = oracle.primal_energy(ref_h, (24, 24, 24), c, f["u"], f["v"], halo=2)
+    D = oracle.dual_energy(ref_h, (24, 24, 24), c, f["u"], f["p"], f["q"], halo=2)
+    assert abs(s["primal"] - P) <= 1e-9 * abs(P)
+    np.testing.assert_allclose(s["parts"], parts, rtol=1e-9)
+    assert abs(s["dual"] - D) <= 1e-9 * max(1.0, abs(D))
+    assert s["nonfinite"] == 0
+
+
+def test_gap_decreases_on_fully_observed_block(ctx):
+    say("gap decreases")
+    rng = np.random.default_rng(3)
+    shape = (8, 8, 8)
+    n = 512
+    hist = np.zeros((n, 8), dtype=np.uint16)
+    for x in range(n):
+        hist[x, :7] = np.bincount(rng.integers(0, 7, size=2 * rng.integers(0, 5) + 1), minlength=7)
+    gaps = []
+    for it in (100, 1000, 10000):
+        _, s = solve_gpu(ctx, hist, shape, it, stats=True)
+        gaps.append(s["gap_rel"])
+    assert gaps[0] > gaps[1] > gaps[2] and gaps[2] < 1e-5
+
+
+def test_zero_iterations_and_alpha_zero_median(ctx):
+    say("iters=0 and alpha=0")
+    rng = np.random.default_rng(9)
+    shape = (9, 7, 5)
+    n = 315
+    hist = np.zeros((n, 8), dtype=np.uint16)
+    for x in range(n):
+        hist[x, :7] = np.bincount(rng.integers(0, 7, size=2 * rng.integers(0, 4) + 1), minlength=7)
+    u0 = rng.uniform(-1, 1, n).astype(np.float32)
+    u, _ = solve_gpu(ctx, hist, shape, 0, u0=u0)
+    assert np.array_equal(u, u0.astype(np.float64))
+    u, _ = solve_gpu(ctx, hist, shape, 100, alpha0=0.0, alpha1=0.0)
+    c = scenes.default_bins()[:7].astype(np.float64)
+    med = np.array([oracle.weighted_median_interval(hist[x, :7].astype(int), c)[0] for x in range(n)])
+    assert np.array_equal(u, np.float32(med).astype(np.float64))
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_half_storage_close_to_oracle(ctx, storage):
+    say("half storage", storage)
+    sc = scenes.sphere_scene()
+    ref_h, _ = oracle.histograms(sc)
+    u16, s = solve_gpu(ctx, ref_h, (32, 32, 32), 300, storage=storage, stats=True)
+    st = oracle.solve(ref_h, (32, 32, 32), scenes.default_bins(), 300)
+    err = np.abs(u16 - st.u).max()
+    say("storage", storage, "max err", err)
+    assert err < 0.05 and s["nonfinite"] == 0
