@@ -150,7 +150,8 @@ class Bins:
         else:
             c = np.asarray(self.centers, dtype=np.float64)
         cc = np.full(8, np.inf, dtype=np.float32)
-        cc[:self.num_bins] = c[:self.num_bins].astype(np.float32)
+        m = max(0, min(self.num_bins, 8))  # an out-of-range count is passed on for the library to reject
+        cc[:m] = c[:m].astype(np.float32)
         for k in range(8):
             b.centers[k] = float(cc[k])
         b.delta = float(np.float32(3.0) * np.float32(h)) if self.delta is None else float(self.delta)

@@ -243,7 +243,9 @@ def test_energy_reduction_matches_oracle_on_same_fields(ctx):
     assert s["nonfinite"] == 0
 
 
-def test_gap_decreases_on_fully_observed_block(ctx):
+def test_gap_decreases_like_the_oracle(ctx):
+    # the relative gap closes at the sublinear rate of the primal-dual method;
+    # the GPU's float64 reduction of its float32 iterates tracks the oracle
     say("gap decreases")
     rng = np.random.default_rng(3)
     shape = (8, 8, 8)
@@ -251,11 +253,18 @@ def test_gap_decreases_on_fully_observed_block(ctx):
     hist = np.zeros((n, 8), dtype=np.uint16)
     for x in range(n):
         hist[x, :7] = np.bincount(rng.integers(0, 7, size=2 * rng.integers(0, 5) + 1), minlength=7)
-    gaps = []
+    gaps, ref = [], []
+    st = None
+    prev = 0
     for it in (100, 1000, 10000):
         _, s = solve_gpu(ctx, hist, shape, it, stats=True)
         gaps.append(s["gap_rel"])
-    assert gaps[0] > gaps[1] > gaps[2] and gaps[2] < 1e-5
+        st = oracle.solve(hist, shape, scenes.default_bins(), it - prev, state=st)
+        prev = it
+        ref.append(oracle.gap(hist, shape, scenes.default_bins(), st)[2])
+    assert gaps[0] > gaps[1] > gaps[2]
+    for a, b in zip(gaps, ref):
+        assert abs(a - b) <= 1e-2 * b + 1e-6, (gaps, ref)
 
 
 def test_zero_iterations_and_alpha_zero_median(ctx):
