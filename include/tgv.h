@@ -85,19 +85,24 @@ typedef struct {
  * arithmetic is float32 in every mode). */
 enum { TGV_STORE_F32 = 0, TGV_STORE_F16 = 1, TGV_STORE_BF16 = 2 };
 
-/* Kernel schedule of a solve: FUSED runs one kernel per iteration (primal
- * then dual in one pass); SPLIT runs the dual and the primal update as two
- * kernels.  Both produce bit-identical results. */
-enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1 };
+/* Kernel schedule of a solve: FUSED runs one tiled kernel per iteration
+ * (primal then dual in one pass over z-marching tiles); SPLIT runs the dual
+ * and the primal update as two per-voxel kernels; FUSED_REF runs the fused
+ * iteration as a per-voxel kernel.  All three produce bit-identical
+ * results. */
+enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1, TGV_SCHED_FUSED_REF = 2 };
 
 /* Solver parameters (Eq. 2, Sec. 3.2).  tau, sigma: primal and dual step
- * sizes (> 0); iters >= 0 primal-dual iterations. */
+ * sizes (> 0); iters >= 0 primal-dual iterations.  tile_y, tile_z: shape of
+ * the fused kernel's tiles (64 x tile_y columns, tile_z planes per
+ * workgroup); 0 picks the library default (tile_y in {4, 8, 12}). */
 typedef struct {
     float alpha0, alpha1, lambda;
     float tau, sigma;
     int32_t iters;
     int32_t storage;   /* TGV_STORE_* */
     int32_t schedule;  /* TGV_SCHED_* */
+    int32_t tile_y, tile_z;
 } tgv_params;
 
 /* Energy statistics of a state, reduced in float64:

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtgv.so")
 
 TGV_OK, TGV_E_INVAL, TGV_E_NOMEM, TGV_E_DEVICE, TGV_E_OVERFLOW, TGV_E_UNSUPPORTED = range(6)
 STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
-SCHED_FUSED, SCHED_SPLIT = 0, 1
+SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF = 0, 1, 2
 STORAGE_NAMES = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
 
 
@@ -55,7 +55,8 @@ class BinsT(ctypes.Structure):
 class ParamsT(ctypes.Structure):
     _fields_ = [("alpha0", ctypes.c_float), ("alpha1", ctypes.c_float), ("lam", ctypes.c_float),
                 ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("iters", ctypes.c_int32),
-                ("storage", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("schedule", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("tile_z", ctypes.c_int32)]
 
 
 class StatsT(ctypes.Structure):
@@ -64,7 +65,7 @@ class StatsT(ctypes.Structure):
 
 
 assert ctypes.sizeof(Camera) == 80 and ctypes.sizeof(GridT) == 32 and ctypes.sizeof(BinsT) == 48
-assert ctypes.sizeof(ParamsT) == 32 and ctypes.sizeof(StatsT) == 64
+assert ctypes.sizeof(ParamsT) == 40 and ctypes.sizeof(StatsT) == 64
 
 _vp = ctypes.c_void_p
 _SIGS = {
@@ -173,12 +174,15 @@ class Params:
     iters: int = 300
     storage: int = STORE_F32
     schedule: int = SCHED_FUSED
+    tile_y: int = 0
+    tile_z: int = 0
 
     def to_c(self) -> ParamsT:
         p = ParamsT()
         p.alpha0, p.alpha1, p.lam = self.alpha0, self.alpha1, self.lam
         p.tau, p.sigma = self.tau, self.sigma
         p.iters, p.storage, p.schedule = int(self.iters), int(self.storage), int(self.schedule)
+        p.tile_y, p.tile_z = int(self.tile_y), int(self.tile_z)
         return p
 
 

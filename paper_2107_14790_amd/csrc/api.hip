@@ -69,7 +69,10 @@ bool params_ok(const tgv_params *p) {
     if (!isfinite(p->alpha0) || !isfinite(p->alpha1) || !isfinite(p->lambda)) return false;
     if (p->iters < 0) return false;
     if (p->storage < 0 || p->storage > 2) return false;
-    if (p->schedule != TGV_SCHED_FUSED && p->schedule != TGV_SCHED_SPLIT) return false;
+    if (p->schedule != TGV_SCHED_FUSED && p->schedule != TGV_SCHED_SPLIT && p->schedule != TGV_SCHED_FUSED_REF)
+        return false;
+    if (p->tile_y < 0 || p->tile_z < 0) return false;
+    if (p->tile_y != 0 && !tiled_shape_ok(p->tile_y, p->tile_z > 0 ? p->tile_z : 1)) return false;
     return true;
 }
 
@@ -92,6 +95,7 @@ Coef make_coef(const tgv_params &p, const tgv_bins &b) {
     c.tau = p.tau;
     c.sigma = p.sigma;
     c.taulam = p.tau * p.lambda;
+    c.taulam2 = 2.0f * c.taulam;
     for (int k = 0; k < 8; k++) c.c[k] = k < b.num_bins ? b.centers[k] : INFINITY;
     return c;
 }
@@ -507,8 +511,12 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
                 st->xc ^= 1;
             }
         } else {
+            int ty = params->tile_y ? params->tile_y : DEFAULT_TILE_Y;
+            int cz = params->tile_z ? params->tile_z : DEFAULT_TILE_Z;
             for (int it = 0; it + 1 < N; it++) {
-                launch_ref(KIND_FUSED, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
+                SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
+                if (params->schedule == TGV_SCHED_FUSED_REF) launch_ref(KIND_FUSED, st->storage, b, d, cf, s);
+                else launch_tiled(st->storage, b, d, cf, ty, cz, s);
                 st->xc ^= 1;
                 st->yc ^= 1;
             }

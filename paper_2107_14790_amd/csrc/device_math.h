@@ -66,13 +66,14 @@ __device__ __forceinline__ bool is_frozen(const Dims &d, int x, int y, int z) {
 
 // Solver constants (float32, as passed through the ABI)
 struct Coef {
-    float alpha0, alpha1, tau, sigma, taulam;
+    float alpha0, alpha1, tau, sigma, taulam, taulam2;  // taulam = tau lambda, taulam2 = 2 tau lambda
     float c[8];  // bin centres, +inf in unused slots
 };
 
 // ---------------------------------------------------------------------------
 // proximal map of lambda sum_k h_k |w - c_k| (step tau):
 //   prox(ut) = max_{k=0..8} min(ut - tau lambda (2 S_k - W), c_k),
+// (the g_k are formed by stepping down from g_0 by 2 tau lambda h_k),
 // S_k = h_0 + ... + h_{k-1}, W = S_8, c_8 = +inf.  On the open interval
 // between c_{k-1} and c_k the optimality condition gives w = ut - tau
 // lambda (2 S_k - W); the max-min form selects that value or the centre
@@ -86,51 +87,40 @@ __device__ __forceinline__ float prox_hist(float ut, const uint32_t hw[4], const
         h[2 * k] = (float)(hw[k] & 0xffffu);
         h[2 * k + 1] = (float)(hw[k] >> 16);
     }
-    float W = 0.0f;
+    float W = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));  // exact: integers
+    // g_k = ut - tau lambda (2 S_k - W), walked down from g_0 = ut + tau lambda W
+    float g = ut + cf.taulam * W;
+    float best = fminf(g, cf.c[0]);
 #pragma unroll
-    for (int k = 0; k < 8; k++) W = W + h[k];
-    float S = 0.0f;
-    float best = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < 8; k++) {
-        float g = ut - cf.taulam * (2.0f * S - W);
+    for (int k = 1; k < 8; k++) {
+        g = g - cf.taulam2 * h[k - 1];
         best = fmaxf(best, fminf(g, cf.c[k]));
-        S = S + h[k];
     }
-    best = fmaxf(best, ut - cf.taulam * W);
-    return best;
+    return fmaxf(best, ut - cf.taulam * W);
 }
 
-// projection onto {|y| <= alpha}: y / max(1, |y| / alpha); alpha = 0 gives 0
+// projection onto {|y| <= alpha}: y / max(1, |y| / alpha), as y * alpha / |y|
+// when |y| > alpha (one reciprocal square root); alpha = 0 gives 0
 __device__ __forceinline__ void project3(float &a, float &b, float &c, float alpha) {
-    if (!(alpha > 0.0f)) {
-        a = b = c = 0.0f;
-        return;
-    }
-    float nrm = sqrtf(a * a + b * b + c * c);
-    float s = nrm / alpha;
-    if (s > 1.0f) {
-        a = a / s;
-        b = b / s;
-        c = c / s;
+    float n2 = a * a + b * b + c * c;
+    if (n2 > alpha * alpha) {
+        float f = alpha * __builtin_amdgcn_rsqf(n2);
+        a = a * f;
+        b = b * f;
+        c = c * f;
     }
 }
 
 // q is a symmetric 3x3 tensor (xx, yy, zz, xy, xz, yz); its norm counts the
 // off-diagonal entries twice (Frobenius norm of the matrix)
 __device__ __forceinline__ void project6(float q[6], float alpha) {
-    if (!(alpha > 0.0f)) {
-#pragma unroll
-        for (int k = 0; k < 6; k++) q[k] = 0.0f;
-        return;
-    }
     float d = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     float o = q[3] * q[3] + q[4] * q[4] + q[5] * q[5];
-    float nrm = sqrtf(d + 2.0f * o);
-    float s = nrm / alpha;
-    if (s > 1.0f) {
+    float n2 = d + 2.0f * o;
+    if (n2 > alpha * alpha) {
+        float f = alpha * __builtin_amdgcn_rsqf(n2);
 #pragma unroll
-        for (int k = 0; k < 6; k++) q[k] = q[k] / s;
+        for (int k = 0; k < 6; k++) q[k] = q[k] * f;
     }
 }
 

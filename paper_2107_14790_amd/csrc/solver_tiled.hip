@@ -1,0 +1,363 @@
+// Fused TGV iteration on z-marching 2.5-D tiles.
+//
+// One workgroup owns a 64 x TY column tile of the block and walks a chunk of
+// CZ planes along z.  Thread (tx, ty) owns the voxel column (x0 + tx,
+// y0 + ty): the values of its column at the previous planes stay in
+// registers, the in-plane neighbours it needs come through LDS.  The ring of
+// columns around the tile (bottom and left rows: v is needed there; top and
+// right rows: u is needed there; two corners: p and q only) is carried by
+// three extra waves, so every thread owns exactly one column.  Per plane s the workgroup
+//   1. publishes p_x, p_y of plane s and q of plane s-1 (LDS), barrier;
+//   2. computes u+ at plane s and v+ at plane s-1 (same per-voxel
+//      arithmetic as the reference kernels), publishes ubar of plane s-1 and
+//      vbar of plane s-1, barrier;
+//   3. computes the dual update of plane s-1 and stores u+, v+, p, q.
+// Each input value is read from memory once per iteration (plus the ring);
+// the next plane is prefetched into registers while the current one is
+// computed.  Barriers wait only for LDS traffic, so the prefetch stays in
+// flight across them.  Results are bit-identical to the reference kernels.
+#include "fields.h"
+#include "internal.h"
+
+namespace tgv {
+
+namespace {
+
+constexpr int TX = 64;
+constexpr unsigned RSRC_WORD3 = 0x00020000u;  // raw buffer, 32-bit data format
+
+// wait for this wave's LDS operations, then meet the workgroup; the memory
+// clobber keeps the compiler from moving LDS accesses across it
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, (int)RSRC_WORD3);
+}
+
+// Field access through buffer descriptors: one descriptor per field array
+// (uniform, in SGPRs); the lane supplies its column's byte offset and the
+// uniform component/plane offset goes in the scalar offset.
+template <int STORE>
+struct Io;
+
+template <>
+struct Io<0> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+    }
+};
+
+template <>
+struct Io<1> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        return __half2float(__ushort_as_half(b));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, 0);
+    }
+};
+
+template <>
+struct Io<2> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        return __uint_as_float(((uint32_t)b) << 16);
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
+        bf16_t t;
+        Store<2>::st(&t, v);
+        __builtin_amdgcn_raw_buffer_store_b16(t.bits, r, voff, soff, 0);
+    }
+};
+
+struct Plane {
+    float u, v[3], p[3], q[6];
+    uint32_t h[4];
+};
+
+// q components the in-plane neighbours read: xx, yy, xy, xz, yz (q slots 0, 1, 3, 4, 5)
+__device__ __forceinline__ int lq_of_slot(int slot) { return slot == 0 ? 0 : (slot == 1 ? 1 : slot - 1); }
+
+template <int STORE, int TY>
+struct Tile {
+    static constexpr int EX = TX + 2, EY = TY + 2, NE = EX * EY;
+    static constexpr int SB = STORE == 0 ? 4 : 2;  // bytes per stored v/p/q element
+    float *sPx, *sPy, *sQ, *sU, *sV;               // LDS planes (sQ: 5 x NE, sV: 3 x NE)
+    __amdgpu_buffer_rsrc_t ru, rv, rp, rq, rh, wu, wv, wp, wq;
+    int comp;                                      // component stride in bytes (n * SB)
+    long long plane4, planeS, planeH;              // plane strides in bytes
+    int v4, vS, vH;                                // the lane's column offsets in bytes
+    const Dims *d;
+    const Coef *cf;
+    int e;                                         // LDS index of the lane's column
+    bool core, needU, needV, in, active;
+    bool mlo_x, mlo_y, mhi_x, mhi_y, fxy;
+    int z0, zl;
+
+    __device__ __forceinline__ void load(Plane &L, int s) const {
+        // planes past the block are clamped to the last one: their values are never used
+        const int sc = s < d->nz ? s : d->nz - 1;
+        const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
+        L.u = Io<0>::ld(ru, v4, o4);
+#pragma unroll
+        for (int c = 0; c < 3; c++) L.v[c] = Io<STORE>::ld(rv, vS, oS + c * comp);
+#pragma unroll
+        for (int c = 0; c < 3; c++) L.p[c] = Io<STORE>::ld(rp, vS, oS + c * comp);
+#pragma unroll
+        for (int c = 0; c < 6; c++) L.q[c] = Io<STORE>::ld(rq, vS, oS + c * comp);
+        auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, vH, oH, 0);
+        L.h[0] = hv[0];
+        L.h[1] = hv[1];
+        L.h[2] = hv[2];
+        L.h[3] = hv[3];
+    }
+
+    // One plane step: prev = plane s-1, cur = plane s, nxt <- plane s+1.
+    // Carried values: UP1/UB1 = u+ and ubar of plane s-1, VB2 = vbar of plane s-2.
+    __device__ __forceinline__ void step(const Plane &prev, const Plane &cur, Plane &nxt, int s, int s1, float &UP1,
+                                         float &UB1, float VB2[3]) const {
+        if (s + 1 <= s1) load(nxt, s + 1);
+        const bool have_s = s < d->nz;
+        const bool do_u = s >= z0 && have_s;
+        const int sv = s - 1;
+        const bool do_v = sv >= max(z0 - 1, 0) && sv <= zl;
+        const bool do_dual = sv >= z0 && sv <= zl;
+
+        // ---- 1. publish p_x, p_y of plane s and q of plane s-1
+        if (active) {
+            sPx[e] = cur.p[0];
+            sPy[e] = cur.p[1];
+            sQ[0 * NE + e] = prev.q[0];
+            sQ[1 * NE + e] = prev.q[1];
+            sQ[2 * NE + e] = prev.q[3];
+            sQ[3 * NE + e] = prev.q[4];
+            sQ[4 * NE + e] = prev.q[5];
+        }
+        lds_barrier();
+
+        // ---- 2. primal updates: u+ at plane s, v+ at plane s-1
+        float UP = 0.0f, UB = 0.0f, VB[3] = {0.0f, 0.0f, 0.0f}, VP[3] = {0.0f, 0.0f, 0.0f};
+        const bool zlo_s = s > 0, zhi_s = s < d->nz - 1;
+        const bool zlo_v = sv > 0, zhi_v = sv < d->nz - 1;
+        if (needU && do_u) {
+            const bool fz = d->halo > 0 && (s < d->halo || s >= d->nz - d->halo);
+            float pm[3];
+            const float lx = sPx[e - 1], ly = sPy[e - EX];
+            pm[0] = mlo_x ? lx : 0.0f;
+            pm[1] = mlo_y ? ly : 0.0f;
+            pm[2] = zlo_s ? prev.p[2] : 0.0f;
+            const bool mlo[3] = {mlo_x, mlo_y, zlo_s}, mhi[3] = {mhi_x, mhi_y, zhi_s};
+            UP = primal_u(cur.u, cur.p, pm, mlo, mhi, fxy || fz, cur.h, *cf);
+            UB = 2.0f * UP - cur.u;
+        }
+        if (needV && do_v) {
+            float qn[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const float ax = sQ[lq_of_slot(qslot(i, 0)) * NE + e + 1];
+                const float ay = sQ[lq_of_slot(qslot(i, 1)) * NE + e + EX];
+                qn[i][0] = mhi_x ? ax : 0.0f;
+                qn[i][1] = mhi_y ? ay : 0.0f;
+                qn[i][2] = zhi_v ? cur.q[qslot(i, 2)] : 0.0f;
+            }
+            const bool mlo[3] = {mlo_x, mlo_y, zlo_v}, mhi[3] = {mhi_x, mhi_y, zhi_v};
+            primal_v(VP, prev.v, prev.p, prev.q, qn, mlo, mhi, *cf);
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                VP[i] = rnd<STORE>(VP[i]);
+                VB[i] = 2.0f * VP[i] - prev.v[i];
+            }
+        }
+        if (needU) sU[e] = UB1;
+        if (needV) {
+            sV[0 * NE + e] = VB[0];
+            sV[1 * NE + e] = VB[1];
+            sV[2 * NE + e] = VB[2];
+        }
+        lds_barrier();
+
+        // ---- 3. dual update of plane s-1 and stores
+        if (core && do_dual) {
+            const bool mlo[3] = {mlo_x, mlo_y, zlo_v}, mhi[3] = {mhi_x, mhi_y, zhi_v};
+            float ub_hi[3], vb_lo[3][3];
+            const float ux = sU[e + 1], uy = sU[e + EX];
+            ub_hi[0] = mhi_x ? ux : 0.0f;
+            ub_hi[1] = mhi_y ? uy : 0.0f;
+            ub_hi[2] = zhi_v ? UB : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const float bx = sV[i * NE + e - 1], by = sV[i * NE + e - EX];
+                vb_lo[0][i] = mlo_x ? bx : 0.0f;
+                vb_lo[1][i] = mlo_y ? by : 0.0f;
+                vb_lo[2][i] = zlo_v ? VB2[i] : 0.0f;
+            }
+            float p[3] = {prev.p[0], prev.p[1], prev.p[2]};
+            float q[6] = {prev.q[0], prev.q[1], prev.q[2], prev.q[3], prev.q[4], prev.q[5]};
+            dual_pq(p, q, UB1, ub_hi, VB, vb_lo, mlo, mhi, *cf);
+            if (in) {
+                const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
+                Io<0>::st(wu, v4, o4, UP1);
+#pragma unroll
+                for (int c = 0; c < 3; c++) Io<STORE>::st(wv, vS, oS + c * comp, VP[c]);
+#pragma unroll
+                for (int c = 0; c < 3; c++) Io<STORE>::st(wp, vS, oS + c * comp, p[c]);
+#pragma unroll
+                for (int c = 0; c < 6; c++) Io<STORE>::st(wq, vS, oS + c * comp, q[c]);
+            }
+        }
+        UP1 = UP;
+        UB1 = UB;
+        VB2[0] = VB[0];
+        VB2[1] = VB[1];
+        VB2[2] = VB[2];
+    }
+};
+
+}  // namespace
+
+template <int STORE, int TY>
+__global__ void __launch_bounds__(TX *(TY + 3)) k_fused_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn,
+                                                              YBuf<STORE> Yn, const uint16_t *__restrict__ hist, Dims d,
+                                                              Coef cf, int CZ, int ntx, int nty, int ntz) {
+    using T = Tile<STORE, TY>;
+    constexpr int EX = T::EX, NE = T::NE;
+    __shared__ float sPx[NE], sPy[NE];
+    __shared__ float sQ[5 * NE];
+    __shared__ float sU[NE];
+    __shared__ float sV[3 * NE];
+
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs;
+    // give each XCD a contiguous run of tiles so neighbours share its L2
+    const int nb = ntx * nty * ntz;
+    const int per = (nb + 7) / 8;
+    const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (L >= nb) return;
+    const int tix = L % ntx, tiy = (L / ntx) % nty, tiz = L / (ntx * nty);
+    const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * CZ;
+
+    // Each thread owns one column of the extended tile.  Waves 0..TY-1: the
+    // tile's rows (dual update and stores); wave TY: the row below (v+
+    // needed); wave TY+1: the row above (u+ needed); wave TY+2: the left
+    // column (v+), the right column (u+) and the two corners read by the
+    // ring (p and q only).
+    const int w = threadIdx.x / TX, lane = threadIdx.x & (TX - 1);
+    int px = -2, py = -2;
+    bool core = false, needU = false, needV = false, active = true;
+    if (w < TY) {
+        px = x0 + lane; py = y0 + w; core = needU = needV = true;
+    } else if (w == TY) {
+        px = x0 + lane; py = y0 - 1; needV = true;
+    } else if (w == TY + 1) {
+        px = x0 + lane; py = y0 + TY; needU = true;
+    } else {
+        if (lane < TY) { px = x0 - 1; py = y0 + lane; needV = true; }
+        else if (lane < 2 * TY) { px = x0 + TX; py = y0 + lane - TY; needU = true; }
+        else if (lane == 2 * TY) { px = x0 - 1; py = y0 + TY; }
+        else if (lane == 2 * TY + 1) { px = x0 + TX; py = y0 - 1; }
+        else active = false;
+    }
+    const bool in = active && px >= 0 && py >= 0 && px < d.nx && py < d.ny;
+
+    T t;
+    t.sPx = sPx;
+    t.sPy = sPy;
+    t.sQ = sQ;
+    t.sU = sU;
+    t.sV = sV;
+    t.d = &d;
+    t.cf = &cf;
+    t.core = core;
+    t.in = in;
+    t.active = active;
+    // columns outside the block compute nothing (their loads are clamped to
+    // column 0 and their results are never read)
+    t.needU = needU && in;
+    t.needV = needV && in;
+    t.core = core && in;
+    t.e = active ? (py - y0 + 1) * EX + (px - x0 + 1) : 0;
+    t.mlo_x = px > 0;
+    t.mlo_y = py > 0;
+    t.mhi_x = px < d.nx - 1;
+    t.mhi_y = py < d.ny - 1;
+    t.fxy = d.halo > 0 && (px < d.halo || py < d.halo || px >= d.nx - d.halo || py >= d.ny - d.halo);
+    t.z0 = z0;
+    t.zl = min(z0 + CZ, d.nz) - 1;
+    const long long col = in ? (long long)px + d.sy * py : 0;
+    t.v4 = (int)(col * 4);
+    t.vS = (int)(col * T::SB);
+    t.vH = (int)(col * 16);
+    t.comp = (int)(d.n * T::SB);
+    t.plane4 = d.sz * 4;
+    t.planeS = d.sz * T::SB;
+    t.planeH = d.sz * 16;
+    t.ru = rsrc(Xc.u, d.n * 4);
+    t.rv = rsrc(Xc.v, 3 * d.n * T::SB);
+    t.rp = rsrc(Yc.p, 3 * d.n * T::SB);
+    t.rq = rsrc(Yc.q, 6 * d.n * T::SB);
+    t.rh = rsrc(hist, d.n * 16);
+    t.wu = rsrc(Xn.u, d.n * 4);
+    t.wv = rsrc(Xn.v, 3 * d.n * T::SB);
+    t.wp = rsrc(Yn.p, 3 * d.n * T::SB);
+    t.wq = rsrc(Yn.q, 6 * d.n * T::SB);
+
+    const int s0 = max(z0 - 1, 0);
+    const int s1 = t.zl + 1;  // may equal nz: that step loads nothing
+    Plane A, B, C;
+    float UP1 = 0.0f, UB1 = 0.0f, VB2[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 3; c++) A.p[c] = A.v[c] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) A.q[c] = 0.0f;
+    t.load(B, s0);
+    // three-plane rotation: (prev, cur, next) = (A, B, C), (B, C, A), (C, A, B)
+    for (int s = s0; s <= s1; s += 3) {
+        t.step(A, B, C, s, s1, UP1, UB1, VB2);
+        if (s + 1 > s1) break;
+        t.step(B, C, A, s + 1, s1, UP1, UB1, VB2);
+        if (s + 2 > s1) break;
+        t.step(C, A, B, s + 2, s1, UP1, UB1, VB2);
+    }
+}
+
+template <int STORE, int TY>
+static void launch_tiled_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
+    XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
+    XBuf<STORE> Xo{b.xo_u, (typename Store<STORE>::T *)b.xo_v};
+    YBuf<STORE> Yc{(typename Store<STORE>::T *)b.yc_p, (typename Store<STORE>::T *)b.yc_q};
+    YBuf<STORE> Yo{(typename Store<STORE>::T *)b.yo_p, (typename Store<STORE>::T *)b.yo_q};
+    int ntx = (d.nx + TX - 1) / TX, nty = (d.ny + TY - 1) / TY, ntz = (d.nz + cz - 1) / cz;
+    int nb = ntx * nty * ntz;
+    int per = (nb + 7) / 8;
+    hipLaunchKernelGGL((k_fused_tiled<STORE, TY>), dim3(8 * per), dim3(TX * (TY + 3)), 0, s, Xc, Yc, Xo, Yo, b.hist, d, cf,
+                       cz, ntx, nty, ntz);
+}
+
+template <int STORE>
+static void launch_tiled_t(const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
+    if (ty == 4) launch_tiled_ty<STORE, 4>(b, d, cf, cz, s);
+    else if (ty == 12) launch_tiled_ty<STORE, 12>(b, d, cf, cz, s);
+    else launch_tiled_ty<STORE, 8>(b, d, cf, cz, s);
+}
+
+bool tiled_shape_ok(int ty, int cz) { return (ty == 4 || ty == 8 || ty == 12) && cz >= 1; }
+
+bool tiled_fits(const Dims &d) {
+    // every byte offset (component * n + plane * nx * ny, in 4-byte elements) must fit a signed 32-bit offset
+    return d.n * 24 < (1LL << 31);
+}
+
+void launch_tiled(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
+    if (!tiled_fits(d)) {
+        launch_ref(KIND_FUSED, storage, b, d, cf, s);
+        return;
+    }
+    if (storage == 0) launch_tiled_t<0>(b, d, cf, ty, cz, s);
+    else if (storage == 1) launch_tiled_t<1>(b, d, cf, ty, cz, s);
+    else launch_tiled_t<2>(b, d, cf, ty, cz, s);
+}
+
+}  // namespace tgv
