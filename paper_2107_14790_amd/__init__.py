@@ -242,8 +242,8 @@ def stats_dict(s: StatsT) -> dict:
 class Context:
     """A libtgv context on one device (owns the library-side workspace)."""
 
-    def __init__(self, device: int = None):
-        self.lib = load_library()
+    def __init__(self, device: int = None, lib_path: str = None):
+        self.lib = load_library() if lib_path is None else load_library(lib_path)
         if not torch.cuda.is_available():
             raise RuntimeError("libtgv needs a ROCm GPU; torch.cuda.is_available() is False")
         self.device = torch.cuda.current_device() if device is None else int(device)
