@@ -55,7 +55,7 @@ struct EnergyOut {
 int64_t storage_bytes(int storage);
 
 void launch_ref(int kind, int storage, const SolveBufs &b, const Dims &d, const Coef &cf, hipStream_t s);
-constexpr int DEFAULT_TILE_Y = 8;
+constexpr int DEFAULT_TILE_Y = 4;
 constexpr int DEFAULT_TILE_Z = 32;
 bool tiled_shape_ok(int ty, int cz);
 void launch_tiled(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);

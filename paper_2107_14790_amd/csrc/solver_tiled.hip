@@ -13,7 +13,7 @@
 //      vbar of plane s-1, barrier;
 //   3. computes the dual update of plane s-1 and stores u+, v+, p, q.
 // Each input value is read from memory once per iteration (plus the ring);
-// the next two planes are in flight in registers while the current one is
+// the next plane is in flight in registers while the current one is
 // computed.  Barriers wait only for LDS traffic, so the prefetch stays in
 // flight across them.  Results are bit-identical to the reference kernels.
 #include "fields.h"
@@ -98,42 +98,35 @@ struct Tile {
     const Dims *d;
     const Coef *cf;
     int e;                                         // LDS index of the lane's column
-    bool core, needU, needV, in, active, ldU, ldV;
+    bool core, needU, needV, in, active;
     bool mlo_x, mlo_y, mhi_x, mhi_y, fxy;
     int z0, zl;
 
-    // Load plane s of the lane's column.  u and the histogram are only read
-    // where u+ is computed, v only where v+ is; p and q everywhere (the ring
-    // publishes them to its neighbours).  ldU / ldV are uniform per wave for
-    // the core and the two ring rows.
+    // Load plane s of the lane's column (every field, for every lane: the
+    // loads stay branch-free so the compiler can issue them back to back).
     __device__ __forceinline__ void load(Plane &L, int s) const {
         // planes past the block are clamped to the last one: their values are never used
         const int sc = s < d->nz ? s : d->nz - 1;
         const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
-        if (ldU) {
-            L.u = Io<0>::ld(ru, v4, o4);
-            auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, vH, oH, 0);
-            L.h[0] = hv[0];
-            L.h[1] = hv[1];
-            L.h[2] = hv[2];
-            L.h[3] = hv[3];
-        }
-        if (ldV) {
+        L.u = Io<0>::ld(ru, v4, o4);
+        auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, vH, oH, 0);
+        L.h[0] = hv[0];
+        L.h[1] = hv[1];
+        L.h[2] = hv[2];
+        L.h[3] = hv[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) L.v[c] = Io<STORE>::ld(rv, vS, oS + c * comp);
-        }
+        for (int c = 0; c < 3; c++) L.v[c] = Io<STORE>::ld(rv, vS, oS + c * comp);
 #pragma unroll
         for (int c = 0; c < 3; c++) L.p[c] = Io<STORE>::ld(rp, vS, oS + c * comp);
 #pragma unroll
         for (int c = 0; c < 6; c++) L.q[c] = Io<STORE>::ld(rq, vS, oS + c * comp);
     }
 
-    // One plane step: prev = plane s-1, cur = plane s (plane s+1 is already
-    // in flight), nxt2 <- plane s+2.  Carried values: UP1/UB1 = u+ and ubar
-    // of plane s-1, VB2 = vbar of plane s-2.
-    __device__ __forceinline__ void step(const Plane &prev, const Plane &cur, Plane &nxt2, int s, int s1, float &UP1,
+    // One plane step: prev = plane s-1, cur = plane s, nxt <- plane s+1.
+    // Carried values: UP1/UB1 = u+ and ubar of plane s-1, VB2 = vbar of plane s-2.
+    __device__ __forceinline__ void step(const Plane &prev, const Plane &cur, Plane &nxt, int s, int s1, float &UP1,
                                          float &UB1, float VB2[3]) const {
-        if (s + 2 <= s1) load(nxt2, s + 2);
+        if (s + 1 <= s1) load(nxt, s + 1);
         const bool have_s = s < d->nz;
         const bool do_u = s >= z0 && have_s;
         const int sv = s - 1;
@@ -290,8 +283,6 @@ __global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_tile
     // column 0 and their results are never read)
     t.needU = needU && in;
     t.needV = needV && in;
-    t.ldU = needU;
-    t.ldV = needV;
     t.core = core && in;
     t.e = active ? (py - y0 + 1) * EX + (px - x0 + 1) : 0;
     t.mlo_x = px > 0;
@@ -321,23 +312,20 @@ __global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_tile
 
     const int s0 = max(z0 - 1, 0);
     const int s1 = t.zl + 1;  // may equal nz: that step loads nothing
-    // four-plane rotation, two planes in flight: plane s0 + k lives in B[k % 4]
-    Plane B0, B1, B2, B3;
+    // three-plane rotation, one plane in flight: (prev, cur, next) = (A, B, C), (B, C, A), (C, A, B)
+    Plane A, B, C;
     float UP1 = 0.0f, UB1 = 0.0f, VB2[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int c = 0; c < 3; c++) B3.p[c] = B3.v[c] = 0.0f;
+    for (int c = 0; c < 3; c++) A.p[c] = A.v[c] = 0.0f;
 #pragma unroll
-    for (int c = 0; c < 6; c++) B3.q[c] = 0.0f;
-    t.load(B0, s0);
-    if (s0 + 1 <= s1) t.load(B1, s0 + 1);
-    for (int s = s0; s <= s1; s += 4) {
-        t.step(B3, B0, B2, s, s1, UP1, UB1, VB2);
+    for (int c = 0; c < 6; c++) A.q[c] = 0.0f;
+    t.load(B, s0);
+    for (int s = s0; s <= s1; s += 3) {
+        t.step(A, B, C, s, s1, UP1, UB1, VB2);
         if (s + 1 > s1) break;
-        t.step(B0, B1, B3, s + 1, s1, UP1, UB1, VB2);
+        t.step(B, C, A, s + 1, s1, UP1, UB1, VB2);
         if (s + 2 > s1) break;
-        t.step(B1, B2, B0, s + 2, s1, UP1, UB1, VB2);
-        if (s + 3 > s1) break;
-        t.step(B2, B3, B1, s + 3, s1, UP1, UB1, VB2);
+        t.step(C, A, B, s + 2, s1, UP1, UB1, VB2);
     }
 }
 

@@ -406,3 +406,228 @@ def config_scene(k: int, **kw) -> Scene:
     if k == 2:
         return terrain_scene(**kw)
     raise ValueError(f"no scene for workload {k}")
+
+
+# ----------------------------------------------------------------------------
+# scene 3: synthetic city (boxes on fBm terrain) seen by oblique cameras
+# ----------------------------------------------------------------------------
+_SCENES_DIR = __import__("os").path.dirname(__import__("os").path.abspath(__file__))
+_RAYLIB = __import__("os").path.join(_SCENES_DIR, "libscenes.so")
+
+
+def build_raycaster() -> str:
+    """Compile the heightfield ray caster (input synthesis only) for gfx950."""
+    import os
+    import subprocess
+    src = os.path.join(_SCENES_DIR, "raycast.hip")
+    tmp = _RAYLIB + ".tmp"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", tmp, src],
+                          stderr=subprocess.DEVNULL)
+    os.replace(tmp, _RAYLIB)
+    return _RAYLIB
+
+
+@dataclasses.dataclass
+class CityHeightfield:
+    """Piecewise-constant heights over the unit square, N x N cells ([j, i])."""
+
+    H: np.ndarray   # [N, N] float32
+    zmin: float
+    zmax: float
+    boxes: np.ndarray  # [n_boxes, 5]: cx, cy, sx, sy, top
+
+
+def city_heightfield(seed: int = 3, lattice: int = 2048, n_boxes: int = 2000, hurst: float = 0.8,
+                     amplitude: float = 0.2) -> CityHeightfield:
+    """fBm terrain (peak-to-peak `amplitude`, mid-height 0.5) carrying
+    axis-aligned boxes: footprint centres U[0.05, 0.95]^2, sides
+    U[0.005, 0.03], heights lognormal (median 0.02, sigma_log 0.6, capped at
+    0.2) above the highest terrain point under the footprint."""
+    rng = np.random.default_rng(seed)
+    z01 = fbm_heightfield(lattice, hurst, seed)
+    H = 0.5 + amplitude * (z01 - 0.5)
+    N = lattice
+    boxes = np.zeros((n_boxes, 5))
+    for b in range(n_boxes):
+        cx, cy = rng.uniform(0.05, 0.95, size=2)
+        sx, sy = rng.uniform(0.005, 0.03, size=2)
+        ht = min(0.2, float(np.exp(np.log(0.02) + 0.6 * rng.normal())))
+        i0, i1 = int((cx - sx / 2) * N), int(np.ceil((cx + sx / 2) * N))
+        j0, j1 = int((cy - sy / 2) * N), int(np.ceil((cy + sy / 2) * N))
+        top = float(H[j0:j1, i0:i1].max()) + ht
+        H[j0:j1, i0:i1] = np.maximum(H[j0:j1, i0:i1], top)
+        boxes[b] = (cx, cy, sx, sy, top)
+    H = H.astype(np.float32)
+    return CityHeightfield(H, float(H.min()), float(H.max()), boxes)
+
+
+def city_cameras(n_side: int = 8, headings: int = 4, W: int = 1024, H: int = 1024, f: float = 1024.0,
+                 tilt_deg: float = 45.0, standoff: float = 0.5, ground: float = 0.5) -> Cameras:
+    """headings x n_side x n_side oblique cameras: each looks at a grid point
+    of the ground plane z = `ground` from `standoff` away along its view
+    direction's horizontal heading, tilted `tilt_deg` from nadir."""
+    Rs, ts = [], []
+    tilt = np.deg2rad(tilt_deg)
+    for hidx in range(headings):
+        th = 2.0 * np.pi * hidx / headings + 0.25 * np.pi
+        dirh = np.array([np.cos(th), np.sin(th)])
+        for j in range(n_side):
+            for i in range(n_side):
+                target = np.array([(i + 0.5) / n_side, (j + 0.5) / n_side, ground])
+                view = np.array([dirh[0] * np.sin(tilt), dirh[1] * np.sin(tilt), -np.cos(tilt)])
+                dist = standoff / np.cos(tilt)
+                C = target - dist * view
+                R, t = look_at(C, target, [0.0, 0.0, 1.0])
+                Rs.append(R)
+                ts.append(t)
+    return make_cameras(Rs, ts, f, f, W / 2.0, H / 2.0, W, H)
+
+
+def _cams_f64(cams: Cameras) -> np.ndarray:
+    n = len(cams)
+    a = np.zeros((n, 16), dtype=np.float64)
+    a[:, 0:9] = cams.R.reshape(n, 9).astype(np.float64)
+    a[:, 9:12] = cams.t.astype(np.float64)
+    a[:, 12:16] = cams.intr.astype(np.float64)
+    return np.ascontiguousarray(a)
+
+
+def render_heightfield_gpu(hf: CityHeightfield, cams: Cameras):
+    """Depth maps [n, H, W] float32 of the heightfield on the GPU (torch tensor)."""
+    import ctypes
+    import os
+    import torch
+    if not os.path.exists(_RAYLIB):
+        raise RuntimeError(f"{_RAYLIB} is not built; run scenes.build_raycaster()")
+    L = ctypes.CDLL(_RAYLIB)
+    L.scenes_raycast.restype = ctypes.c_int
+    L.scenes_raycast.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    Hd = torch.from_numpy(hf.H).cuda()
+    W, Hh = (int(v) for v in cams.wh[0])
+    out = torch.empty((len(cams), Hh, W), dtype=torch.float32, device="cuda")
+    ca = _cams_f64(cams)
+    st = torch.cuda.current_stream().cuda_stream
+    rc = L.scenes_raycast(Hd.data_ptr(), hf.H.shape[0], hf.zmin, hf.zmax, ca.ctypes.data, len(cams), W, Hh,
+                          out.data_ptr(), ctypes.c_void_p(st))
+    if rc != 0:
+        raise RuntimeError(f"scenes_raycast failed ({rc})")
+    return out
+
+
+def render_heightfield_cpu(hf: CityHeightfield, cams: Cameras) -> np.ndarray:
+    """The same cell walk in numpy (vectorised over rays), for small images."""
+    N = hf.H.shape[0]
+    W, Hh = (int(v) for v in cams.wh[0])
+    out = np.zeros((len(cams), Hh, W), dtype=np.float32)
+    Hf = hf.H.astype(np.float64)
+    for k in range(len(cams)):
+        C, d = pixel_rays(cams, k)
+        d = d.reshape(-1, 3)
+        nr = d.shape[0]
+        lo = np.array([0.0, 0.0, hf.zmin])
+        hi = np.array([1.0, 1.0, hf.zmax])
+        t0 = np.full(nr, 1e-9)
+        t1 = np.full(nr, 1e30)
+        miss = np.zeros(nr, dtype=bool)
+        for a in range(3):
+            small = np.abs(d[:, a]) < 1e-300
+            miss |= small & ((C[a] < lo[a]) | (C[a] > hi[a]))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                ta = (lo[a] - C[a]) / d[:, a]
+                tb = (hi[a] - C[a]) / d[:, a]
+            tmin = np.where(small, -np.inf, np.minimum(ta, tb))
+            tmax = np.where(small, np.inf, np.maximum(ta, tb))
+            t0 = np.maximum(t0, tmin)
+            t1 = np.minimum(t1, tmax)
+        alive = ~miss & (t0 < t1)
+        x = C[0] + t0 * d[:, 0]
+        y = C[1] + t0 * d[:, 1]
+        ci = np.clip(np.floor(x * N).astype(np.int64), 0, N - 1)
+        cj = np.clip(np.floor(y * N).astype(np.int64), 0, N - 1)
+        si = np.where(d[:, 0] > 0, 1, -1)
+        sj = np.where(d[:, 1] > 0, 1, -1)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tdx = np.where(np.abs(d[:, 0]) > 1e-300, 1.0 / (N * np.abs(d[:, 0])), 1e300)
+            tdy = np.where(np.abs(d[:, 1]) > 1e-300, 1.0 / (N * np.abs(d[:, 1])), 1e300)
+            tmx = np.where(np.abs(d[:, 0]) > 1e-300, ((ci + (si > 0)) / N - C[0]) / d[:, 0], 1e300)
+            tmy = np.where(np.abs(d[:, 1]) > 1e-300, ((cj + (sj > 0)) / N - C[1]) / d[:, 1], 1e300)
+        tc = t0.copy()
+        res = np.zeros(nr)
+        for _ in range(4 * N + 8):
+            if not alive.any():
+                break
+            te = np.minimum(np.minimum(tmx, tmy), t1)
+            h = Hf[np.clip(cj, 0, N - 1), np.clip(ci, 0, N - 1)]
+            zin = C[2] + tc * d[:, 2]
+            zout = C[2] + te * d[:, 2]
+            hit = alive & (np.minimum(zin, zout) <= h)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                th = np.where(zin <= h, tc, (h - C[2]) / d[:, 2])
+            res = np.where(hit, th, res)
+            alive &= ~hit
+            alive &= te < t1
+            tc = np.where(alive, te, tc)
+            stepx = tmx < tmy
+            ci = np.where(alive & stepx, ci + si, ci)
+            tmx = np.where(alive & stepx, tmx + tdx, tmx)
+            cj = np.where(alive & ~stepx, cj + sj, cj)
+            tmy = np.where(alive & ~stepx, tmy + tdy, tmy)
+            alive &= (ci >= 0) & (cj >= 0) & (ci < N) & (cj < N)
+        out[k] = res.reshape(Hh, W).astype(np.float32)
+    return out
+
+
+def city_scene(seed: int = 3, lattice: int = 2048, n_boxes: int = 2000, W: int = 1024, H: int = 1024,
+               f: float = 1024.0, n_side: int = 8, headings: int = 4, sigma: float = 0.3 / 1024,
+               outlier_frac: float = 0.01, device: str = "cuda", grid: Grid = None):
+    """City depth maps (returned as a Scene with a placeholder grid unless one
+    is given) plus the heightfield.  Noise: N(0, sigma^2) on z and uniform
+    outliers over the camera-z range of the unit cube."""
+    hf = city_heightfield(seed, lattice, n_boxes)
+    cams = city_cameras(n_side, headings, W, H, f)
+    if device == "cuda":
+        clean = render_heightfield_gpu(hf, cams).cpu().numpy().astype(np.float64)
+    else:
+        clean = render_heightfield_cpu(hf, cams).astype(np.float64)
+    g = grid if grid is not None else Grid(np.zeros(3, dtype=np.float32), float(np.float32(1.0 / 256)), (256, 256, 256))
+    rng = np.random.default_rng(seed + 7000)
+    depth = add_noise(clean, cams, Grid(np.zeros(3, dtype=np.float32), 1.0, (1, 1, 1)), sigma, outlier_frac, rng)
+    return Scene(depth, cams, g, name="city"), hf
+
+
+def city_blocks(scene: Scene, n_blocks: int = 512, e_min: int = 32, e_max: int = 128, halo: int = 2,
+                h0: float = 1.0 / 1024, seed: int = 4):
+    """Octree-leaf-like blocks on the visible city surface: interior edge
+    e = round(exp U[ln e_min, ln e_max]) voxels plus `halo` on each side;
+    centres on surface points seen by random cameras; voxel size h0 * 2^m
+    with m in 0..3 growing with the distance to the nearest camera (8x range)."""
+    rng = np.random.default_rng(seed)
+    cams = scene.cams
+    Cs = cams.centers()
+    blocks = []
+    tries = 0
+    while len(blocks) < n_blocks and tries < 100 * n_blocks:
+        tries += 1
+        k = int(rng.integers(len(cams)))
+        W, H = (int(v) for v in cams.wh[k])
+        px, py = int(rng.integers(W)), int(rng.integers(H))
+        z = float(scene.depth[k, py, px])
+        if not z > 0:
+            continue
+        C, d = pixel_rays(cams, k)
+        P = C + z * d[py, px]
+        dist = float(np.min(np.linalg.norm(Cs - P[None, :], axis=1)))
+        e = int(round(np.exp(rng.uniform(np.log(e_min), np.log(e_max)))))
+        blocks.append((P, dist, e))
+    dists = np.array([b[1] for b in blocks])
+    q = np.quantile(dists, [0.25, 0.5, 0.75])
+    out = []
+    for P, dist, e in blocks:
+        m = int(np.searchsorted(q, dist))
+        h = float(np.float32(h0 * (2 ** m)))
+        n = e + 2 * halo
+        origin = (P - 0.5 * n * h).astype(np.float32)
+        out.append(Grid(origin, h, (n, n, n), halo))
+    return out
