@@ -103,7 +103,11 @@ typedef struct {
     int32_t storage;   /* TGV_STORE_* */
     int32_t schedule;  /* TGV_SCHED_* */
     int32_t tile_y, tile_z;
+    int32_t flags;     /* TGV_FLAG_* */
 } tgv_params;
+
+/* flags: capture a batched solve's iteration loop in a HIP graph and replay it */
+enum { TGV_FLAG_GRAPH = 1 };
 
 /* Energy statistics of a state, reduced in float64:
  *   primal = discrete Eq. 2 at (u, v);
@@ -205,6 +209,21 @@ tgv_status tgv_state_import(tgv_ctx *ctx, tgv_state *st, const float *u, const f
  * state (this synchronises the stream). */
 tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
                      const tgv_params *params, float *u_io, tgv_state *state, tgv_stats *stats_host, void *stream);
+
+/* Batched solve (many uneven blocks, Sec. 4.5: treetop leaves are
+ * independent units, and small ones are processed together): advance each
+ * of the n states by params->iters iterations.  Every iteration of all
+ * blocks is one persistent launch whose workgroups pull tiles from a device
+ * work queue (plus a per-block dual step at the start and primal step at
+ * the end).  hist: host array of n device pointers (block i's histograms);
+ * tile_z_host: per-block z-chunk of the tiles (NULL = params->tile_z or the
+ * default); params->tile_y applies to all blocks.  With TGV_FLAG_GRAPH the
+ * iteration loop is captured once in a HIP graph and replayed.  Results are
+ * bit-identical to tgv_solve on each state alone.  stats_host: NULL or n
+ * entries (synchronises).  All states must use params->storage. */
+tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const *states, const uint16_t *const *hist,
+                           const tgv_bins *bins, const tgv_params *params, const int32_t *tile_z_host,
+                           tgv_stats *stats_host, void *stream);
 
 /* Energy statistics of a state (synchronises the stream). */
 tgv_status tgv_energy(tgv_ctx *ctx, const tgv_state *st, const uint16_t *hist, const tgv_bins *bins,

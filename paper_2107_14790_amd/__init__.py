@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libtgv.so")
 TGV_OK, TGV_E_INVAL, TGV_E_NOMEM, TGV_E_DEVICE, TGV_E_OVERFLOW, TGV_E_UNSUPPORTED = range(6)
 STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF = 0, 1, 2
+FLAG_GRAPH = 1
 STORAGE_NAMES = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
 
 
@@ -56,7 +57,7 @@ class ParamsT(ctypes.Structure):
     _fields_ = [("alpha0", ctypes.c_float), ("alpha1", ctypes.c_float), ("lam", ctypes.c_float),
                 ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("iters", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("schedule", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("tile_z", ctypes.c_int32)]
+                ("tile_z", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class StatsT(ctypes.Structure):
@@ -65,7 +66,7 @@ class StatsT(ctypes.Structure):
 
 
 assert ctypes.sizeof(Camera) == 80 and ctypes.sizeof(GridT) == 32 and ctypes.sizeof(BinsT) == 48
-assert ctypes.sizeof(ParamsT) == 40 and ctypes.sizeof(StatsT) == 64
+assert ctypes.sizeof(ParamsT) == 44 and ctypes.sizeof(StatsT) == 64
 
 _vp = ctypes.c_void_p
 _SIGS = {
@@ -89,6 +90,9 @@ _SIGS = {
                                  _vp, _vp, ctypes.POINTER(StatsT), _vp]),
     "tgv_energy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT),
                                   ctypes.POINTER(StatsT), _vp]),
+    "tgv_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                       ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(StatsT), _vp]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -176,6 +180,7 @@ class Params:
     schedule: int = SCHED_FUSED
     tile_y: int = 0
     tile_z: int = 0
+    flags: int = 0
 
     def to_c(self) -> ParamsT:
         p = ParamsT()
@@ -183,6 +188,7 @@ class Params:
         p.tau, p.sigma = self.tau, self.sigma
         p.iters, p.storage, p.schedule = int(self.iters), int(self.storage), int(self.schedule)
         p.tile_y, p.tile_z = int(self.tile_y), int(self.tile_z)
+        p.flags = int(self.flags)
         return p
 
 
@@ -324,6 +330,27 @@ class Context:
                                        _ptr(u_io), state.h if state is not None else None,
                                        ctypes.byref(s) if stats else None, _stream(stream)))
         return stats_dict(s) if stats else None
+
+    def solve_batch(self, states, hists, params: Params = None, bins: Bins = None, tile_z=None, stats: bool = False,
+                    stream=None):
+        """Advance every state by params.iters iterations in batched launches
+        (bit-identical to solving each alone).  hists: device tensors, one per
+        state.  tile_z: optional per-block z-chunk list.  Returns per-block
+        stats when stats=True (synchronises)."""
+        n = len(states)
+        if len(hists) != n:
+            raise ValueError("one histogram tensor per state")
+        p = (params or Params()).to_c()
+        b = (bins or Bins()).to_c(states[0].grid.h if n else 1.0)
+        sarr = (_vp * max(n, 1))(*[s.h for s in states])
+        harr = (_vp * max(n, 1))(*[_ptr(h) for h in hists])
+        tz = None
+        if tile_z is not None:
+            tz = (ctypes.c_int32 * max(n, 1))(*[int(v) for v in tile_z])
+        st = (StatsT * max(n, 1))()
+        self._check(self.lib.tgv_solve_batch(self.h, n, sarr, harr, ctypes.byref(b), ctypes.byref(p), tz,
+                                             st if stats else None, _stream(stream)))
+        return [stats_dict(st[i]) for i in range(n)] if stats else None
 
     def energy(self, state: "State", hist: torch.Tensor, params: Params = None, bins: Bins = None,
                stream=None) -> dict:

@@ -72,6 +72,7 @@ bool params_ok(const tgv_params *p) {
     if (p->schedule != TGV_SCHED_FUSED && p->schedule != TGV_SCHED_SPLIT && p->schedule != TGV_SCHED_FUSED_REF)
         return false;
     if (p->tile_y < 0 || p->tile_z < 0) return false;
+    if (p->flags & ~TGV_FLAG_GRAPH) return false;
     if (p->tile_y != 0 && !tiled_shape_ok(p->tile_y, p->tile_z > 0 ? p->tile_z : 1)) return false;
     return true;
 }
@@ -137,7 +138,22 @@ extern "C" tgv_status tgv_create(int device, tgv_ctx **out) {
     c->eout_dev = nullptr;
     c->eout_host = nullptr;
     c->own = nullptr;
+    c->bt_blocks_dev = nullptr;
+    c->bt_tiles_dev = nullptr;
+    c->bt_blocks_host = nullptr;
+    c->bt_tiles_host = nullptr;
+    c->bt_blocks_cap = 0;
+    c->bt_tiles_cap = 0;
+    c->counters = nullptr;
+    c->graph_exec = nullptr;
+    c->graph_key.clear();
+    c->side = nullptr;
     if (hipEventCreateWithFlags(&c->cams_evt, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->bt_evt, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc((void **)&c->counters, 64 * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->eout_dev, sizeof(EnergyOut)) != hipSuccess ||
         hipHostMalloc((void **)&c->eout_host, sizeof(EnergyOut), hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -158,6 +174,16 @@ extern "C" void tgv_destroy(tgv_ctx *c) {
     (void)hipFree(c->eout_dev);
     (void)hipHostFree(c->eout_host);
     (void)hipEventDestroy(c->cams_evt);
+    (void)hipEventDestroy(c->bt_evt);
+    (void)hipEventDestroy(c->ev_a);
+    (void)hipEventDestroy(c->ev_b);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    (void)hipStreamDestroy(c->side);
+    (void)hipFree(c->counters);
+    (void)hipFree(c->bt_blocks_dev);
+    (void)hipFree(c->bt_tiles_dev);
+    (void)hipHostFree(c->bt_blocks_host);
+    (void)hipHostFree(c->bt_tiles_host);
     delete c;
 }
 
@@ -530,5 +556,204 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
     }
     if (u_io) HIP_TRY(ctx, hipMemcpyAsync(u_io, st->u[st->xc], 4 * st->n, hipMemcpyDeviceToDevice, s));
     if (stats_host) return run_energy(ctx, st, hist, bins, params, stats_host, s);
+    return TGV_OK;
+}
+
+
+// ===========================================================================
+// batched solve
+// ===========================================================================
+static int persistent_grid(tgv_ctx *ctx, int ty, int ntiles) {
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    // workgroups per CU the tiled kernel sustains (VGPR- and LDS-limited): 7-wave
+    // groups fit 3 per CU, 11-wave groups 2, 15-wave groups 1
+    int per_cu = ty == 4 ? 3 : (ty == 8 ? 2 : 1);
+    int g = cus * per_cu;
+    g = (g + 7) / 8 * 8;
+    int cap = (ntiles + 7) / 8 * 8;
+    return g < cap ? g : cap;
+}
+
+extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const *states, const uint16_t *const *hist,
+                                      const tgv_bins *bins, const tgv_params *params, const int32_t *tile_z_host,
+                                      tgv_stats *stats_host, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (n < 0 || (n > 0 && (!states || !hist))) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: bad arguments");
+    if (!bins_ok(bins)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: bad bins");
+    if (!params_ok(params)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: bad params");
+    for (int i = 0; i < n; i++) {
+        if (!states[i] || !hist[i]) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: null state or hist %d", i);
+        if (states[i]->storage != params->storage)
+            return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: state %d storage %d != %d", i, states[i]->storage,
+                        params->storage);
+        if (tile_z_host && tile_z_host[i] < 1) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: tile_z[%d] < 1", i);
+        for (int j = 0; j < i; j++)
+            if (states[j] == states[i]) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: state %d repeated", i);
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = S(stream);
+    Coef cf = make_coef(*params, *bins);
+    const int N = params->iters;
+    const int ty = params->tile_y ? params->tile_y : DEFAULT_TILE_Y;
+    if (!tiled_shape_ok(ty, 1)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: tile_y %d", ty);
+    if (n == 0 || N == 0) {
+        if (stats_host)
+            for (int i = 0; i < n; i++) {
+                tgv_status r = run_energy(ctx, states[i], hist[i], bins, params, &stats_host[i], s);
+                if (r != TGV_OK) return r;
+            }
+        return TGV_OK;
+    }
+    // 1. dual step of every block (in place)
+    for (int i = 0; i < n; i++) {
+        tgv_state *st = states[i];
+        SolveBufs b = bufs_of(st, st->xc, st->yc, hist[i]);
+        if (st->fresh) {
+            b.xo_u = b.xc_u;
+            b.xo_v = b.xc_v;
+        }
+        launch_ref(KIND_DUAL, st->storage, b, make_dims(st->grid), cf, s);
+    }
+    // 2. block and tile tables (blocks too large for 32-bit tile offsets run alone)
+    std::vector<int> big;
+    HIP_TRY(ctx, hipEventSynchronize(ctx->bt_evt));  // the previous upload has left the staging buffers
+    int nb = 0, nt = 0;
+    {
+        long long tiles = 0;
+        for (int i = 0; i < n; i++) {
+            Dims d = make_dims(states[i]->grid);
+            if (!tiled_fits(d)) continue;
+            int cz = tile_z_host ? tile_z_host[i] : (params->tile_z ? params->tile_z : DEFAULT_TILE_Z);
+            tiles += (long long)((d.nx + 63) / 64) * ((d.ny + ty - 1) / ty) * ((d.nz + cz - 1) / cz);
+        }
+        if (tiles > (1LL << 30)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: too many tiles");
+        if (n > ctx->bt_blocks_cap) {
+            (void)hipFree(ctx->bt_blocks_dev);
+            (void)hipHostFree(ctx->bt_blocks_host);
+            ctx->bt_blocks_dev = nullptr;
+            ctx->bt_blocks_host = nullptr;
+            ctx->bt_blocks_cap = 0;
+            HIP_TRY(ctx, hipMalloc((void **)&ctx->bt_blocks_dev, sizeof(BatchBlock) * n));
+            HIP_TRY(ctx, hipHostMalloc((void **)&ctx->bt_blocks_host, sizeof(BatchBlock) * n, hipHostMallocDefault));
+            ctx->bt_blocks_cap = n;
+        }
+        if (tiles > ctx->bt_tiles_cap) {
+            (void)hipFree(ctx->bt_tiles_dev);
+            (void)hipHostFree(ctx->bt_tiles_host);
+            ctx->bt_tiles_dev = nullptr;
+            ctx->bt_tiles_host = nullptr;
+            ctx->bt_tiles_cap = 0;
+            HIP_TRY(ctx, hipMalloc((void **)&ctx->bt_tiles_dev, sizeof(int4) * tiles));
+            HIP_TRY(ctx, hipHostMalloc((void **)&ctx->bt_tiles_host, sizeof(int4) * tiles, hipHostMallocDefault));
+            ctx->bt_tiles_cap = (int)tiles;
+        }
+        for (int i = 0; i < n; i++) {
+            tgv_state *st = states[i];
+            Dims d = make_dims(st->grid);
+            if (!tiled_fits(d)) {
+                big.push_back(i);
+                continue;
+            }
+            int cz = tile_z_host ? tile_z_host[i] : (params->tile_z ? params->tile_z : DEFAULT_TILE_Z);
+            BatchBlock &bb = ctx->bt_blocks_host[nb];
+            for (int k = 0; k < 2; k++) {
+                bb.u[k] = st->u[k];
+                bb.v[k] = st->v[k];
+                bb.p[k] = st->p[k];
+                bb.q[k] = st->q[k];
+            }
+            bb.hist = hist[i];
+            bb.d = d;
+            bb.cz = cz;
+            bb.xc = st->xc;
+            bb.yc = st->yc;
+            bb.pad = 0;
+            int ntx = (d.nx + 63) / 64, nty = (d.ny + ty - 1) / ty, ntz = (d.nz + cz - 1) / cz;
+            for (int z = 0; z < ntz; z++)
+                for (int y = 0; y < nty; y++)
+                    for (int x = 0; x < ntx; x++) ctx->bt_tiles_host[nt++] = make_int4(nb, x | (y << 16), z, 0);
+            nb++;
+        }
+    }
+    if (nb > 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->bt_blocks_dev, ctx->bt_blocks_host, sizeof(BatchBlock) * nb,
+                                    hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->bt_tiles_dev, ctx->bt_tiles_host, sizeof(int4) * nt, hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, hipEventRecord(ctx->bt_evt, s));
+    }
+    // 3. N-1 fused iterations of all blocks: one persistent launch each
+    const int grid = persistent_grid(ctx, ty, nt);
+    const int F = N - 1;
+    if (nb > 0 && F > 0) {
+        const bool use_graph = (params->flags & TGV_FLAG_GRAPH) && F >= 2;
+        if (!use_graph) {
+            for (int it = 0; it < F; it++)
+                launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters,
+                             cf, ty, it & 1, grid, s);
+        } else {
+            // the graph holds two iterations (parity 0 then 1); it is keyed by
+            // everything its kernel arguments capture
+            char key[256];
+            int kl = snprintf(key, sizeof(key), "%d|%d|%d|%d|%d|", params->storage, ty, nt, grid, nb);
+            std::string k(key, kl);
+            k.append((const char *)&cf, sizeof(cf));
+            HIP_TRY(ctx, hipEventRecord(ctx->ev_a, s));
+            HIP_TRY(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_a, 0));
+            if (!ctx->graph_exec || ctx->graph_key != k) {
+                if (ctx->graph_exec) {
+                    (void)hipGraphExecDestroy(ctx->graph_exec);
+                    ctx->graph_exec = nullptr;
+                }
+                hipGraph_t g = nullptr;
+                HIP_TRY(ctx, hipStreamBeginCapture(ctx->side, hipStreamCaptureModeThreadLocal));
+                for (int it = 0; it < 2; it++)
+                    launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt,
+                                 ctx->counters, cf, ty, it, grid, ctx->side);
+                HIP_TRY(ctx, hipStreamEndCapture(ctx->side, &g));
+                hipError_t e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    ctx->graph_exec = nullptr;
+                    return fail(ctx, TGV_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+                }
+                ctx->graph_key = k;
+            }
+            for (int r = 0; r < F / 2; r++) HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->side));
+            if (F & 1)
+                launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters,
+                             cf, ty, 0, grid, ctx->side);
+            HIP_TRY(ctx, hipEventRecord(ctx->ev_b, ctx->side));
+            HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->ev_b, 0));
+        }
+    }
+    // blocks too large for the batched kernel: their own fused launches
+    for (int i : big) {
+        tgv_state *st = states[i];
+        Dims d = make_dims(st->grid);
+        int xc = st->xc, yc = st->yc;
+        for (int it = 0; it < F; it++) {
+            launch_ref(KIND_FUSED, st->storage, bufs_of(st, xc, yc, hist[i]), d, cf, s);
+            xc ^= 1;
+            yc ^= 1;
+        }
+    }
+    // 4. parities after F fused iterations, then the closing primal step
+    for (int i = 0; i < n; i++) {
+        tgv_state *st = states[i];
+        st->xc ^= (F & 1);
+        st->yc ^= (F & 1);
+        launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist[i]), make_dims(st->grid), cf, s);
+        st->xc ^= 1;
+        st->fresh = false;
+        st->iters_done += N;
+    }
+    tgv_status r = check_launch(ctx, "batched solve");
+    if (r != TGV_OK) return r;
+    if (stats_host)
+        for (int i = 0; i < n; i++) {
+            r = run_energy(ctx, states[i], hist[i], bins, params, &stats_host[i], s);
+            if (r != TGV_OK) return r;
+        }
     return TGV_OK;
 }

@@ -26,6 +26,20 @@ struct SolveBufs {
     const uint16_t *hist;
 };
 
+// One block of a batched solve as the persistent kernel reads it: the
+// state's buffers for both parities and the block's current parities.
+struct BatchBlock {
+    float *u[2];
+    void *v[2];
+    void *p[2];
+    void *q[2];
+    const uint16_t *hist;
+    Dims d;
+    int cz;
+    int xc, yc;
+    int pad;
+};
+
 // Geometry of a packed pyramid (all cameras the same size).
 struct PyrGeom {
     int L;
@@ -59,6 +73,10 @@ constexpr int DEFAULT_TILE_Y = 4;
 constexpr int DEFAULT_TILE_Z = 32;
 bool tiled_shape_ok(int ty, int cz);
 void launch_tiled(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);
+bool tiled_fits(const Dims &d);
+// one fused iteration of every block listed in `tiles` (int4: block, tix | tiy << 16, tiz, 0)
+void launch_batch(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
+                  int ty, int flip, int grid, hipStream_t s);
 void launch_energy(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, float lambda, double vbound,
                    double *partials, int nparts, EnergyOut *out, hipStream_t s);
 int energy_partials(const Dims &d);
@@ -88,6 +106,16 @@ struct tgv_ctx {
     tgv::EnergyOut *eout_host;
     // state used by tgv_solve when the caller passes none
     tgv_state *own;
+    // batched solves: block and tile tables, queue counters, captured graph
+    tgv::BatchBlock *bt_blocks_dev, *bt_blocks_host;
+    int4 *bt_tiles_dev, *bt_tiles_host;
+    int bt_blocks_cap, bt_tiles_cap;
+    hipEvent_t bt_evt;
+    int *counters;
+    hipGraphExec_t graph_exec;
+    std::string graph_key;
+    hipStream_t side;
+    hipEvent_t ev_a, ev_b;
 };
 
 struct tgv_state {

@@ -225,24 +225,25 @@ struct Tile {
 
 }  // namespace
 
-template <int STORE, int TY>
-__global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn,
-                                                              YBuf<STORE> Yn, const uint16_t *__restrict__ hist, Dims d,
-                                                              Coef cf, int CZ, int ntx, int nty, int ntz) {
-    using T = Tile<STORE, TY>;
-    constexpr int EX = T::EX, NE = T::NE;
-    __shared__ float sPx[NE], sPy[NE];
-    __shared__ float sQ[5 * NE];
-    __shared__ float sU[NE];
-    __shared__ float sV[3 * NE];
+// LDS planes of one tile
+template <int TY>
+struct TileLds {
+    static constexpr int NE = (TX + 2) * (TY + 2);
+    float sPx[NE], sPy[NE];
+    float sQ[5 * NE];
+    float sU[NE];
+    float sV[3 * NE];
+};
 
-    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs;
-    // give each XCD a contiguous run of tiles so neighbours share its L2
-    const int nb = ntx * nty * ntz;
-    const int per = (nb + 7) / 8;
-    const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (L >= nb) return;
-    const int tix = L % ntx, tiy = (L / ntx) % nty, tiz = L / (ntx * nty);
+// One fused iteration on tile (tix, tiy, tiz) of a block: X/Y current
+// buffers in, Xn/Yn out.  Every thread of the workgroup must call this
+// (it contains workgroup barriers).
+template <int STORE, int TY>
+__device__ __forceinline__ void run_tile(TileLds<TY> &lds, const XBuf<STORE> &Xc, const YBuf<STORE> &Yc,
+                                         const XBuf<STORE> &Xn, const YBuf<STORE> &Yn, const uint16_t *hist,
+                                         const Dims &d, const Coef &cf, int CZ, int tix, int tiy, int tiz) {
+    using T = Tile<STORE, TY>;
+    constexpr int EX = T::EX;
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * CZ;
 
     // Each thread owns one column of the extended tile.  Waves 0..TY-1: the
@@ -269,14 +270,13 @@ __global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_tile
     const bool in = active && px >= 0 && py >= 0 && px < d.nx && py < d.ny;
 
     T t;
-    t.sPx = sPx;
-    t.sPy = sPy;
-    t.sQ = sQ;
-    t.sU = sU;
-    t.sV = sV;
+    t.sPx = lds.sPx;
+    t.sPy = lds.sPy;
+    t.sQ = lds.sQ;
+    t.sU = lds.sU;
+    t.sV = lds.sV;
     t.d = &d;
     t.cf = &cf;
-    t.core = core;
     t.in = in;
     t.active = active;
     // columns outside the block compute nothing (their loads are clamped to
@@ -330,6 +330,64 @@ __global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_tile
 }
 
 template <int STORE, int TY>
+__global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc,
+                                                                                  XBuf<STORE> Xn, YBuf<STORE> Yn,
+                                                                                  const uint16_t *__restrict__ hist,
+                                                                                  Dims d, Coef cf, int CZ, int ntx,
+                                                                                  int nty, int ntz) {
+    __shared__ TileLds<TY> lds;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs;
+    // give each XCD a contiguous run of tiles so neighbours share its L2
+    const int nb = ntx * nty * ntz;
+    const int per = (nb + 7) / 8;
+    const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (L >= nb) return;
+    run_tile<STORE, TY>(lds, Xc, Yc, Xn, Yn, hist, d, cf, CZ, L % ntx, (L / ntx) % nty, L / (ntx * nty));
+}
+
+// ---------------------------------------------------------------------------
+// batched fused iteration: many blocks in one persistent launch
+// ---------------------------------------------------------------------------
+// Workgroups pull tiles from a device work queue split into 8 segments (one
+// per XCD, so the tiles of a block stay near each other's L2); a workgroup
+// drains its own segment, then takes from the others.  Every tile of every
+// block advances one iteration per launch; no workgroup waits on another.
+template <int STORE, int TY>
+__global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_batch(const BatchBlock *__restrict__ blocks,
+                                                                                  const int4 *__restrict__ tiles,
+                                                                                  int ntiles, int *counters, Coef cf,
+                                                                                  int flip) {
+    __shared__ TileLds<TY> lds;
+    __shared__ int s_tile;
+    const int seg_len = (ntiles + 7) / 8;
+    const int home = (int)(blockIdx.x % 8);
+    for (int k = 0; k < 8; k++) {
+        const int seg = (home + k) & 7;
+        const int seg_end = min(seg_len * (seg + 1), ntiles);
+        while (true) {
+            if (threadIdx.x == 0) s_tile = seg * seg_len + atomicAdd(&counters[seg], 1);
+            lds_barrier();
+            const int ti = s_tile;
+            lds_barrier();  // everyone has read s_tile before it is rewritten
+            if (ti >= seg_end) break;
+            const int4 tr = tiles[ti];
+            const BatchBlock &bb = blocks[tr.x];
+            const int xc = bb.xc ^ flip, yc = bb.yc ^ flip;
+            XBuf<STORE> Xc{bb.u[xc], (typename Store<STORE>::T *)bb.v[xc]};
+            XBuf<STORE> Xn{bb.u[xc ^ 1], (typename Store<STORE>::T *)bb.v[xc ^ 1]};
+            YBuf<STORE> Yc{(typename Store<STORE>::T *)bb.p[yc], (typename Store<STORE>::T *)bb.q[yc]};
+            YBuf<STORE> Yn{(typename Store<STORE>::T *)bb.p[yc ^ 1], (typename Store<STORE>::T *)bb.q[yc ^ 1]};
+            run_tile<STORE, TY>(lds, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz, tr.y & 0xffff, tr.y >> 16, tr.z);
+            lds_barrier();  // the tile's LDS reads are done before the next tile writes
+        }
+    }
+}
+
+__global__ void k_reset_counters(int *counters) {
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+}
+
+template <int STORE, int TY>
 static void launch_tiled_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
     XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
     XBuf<STORE> Xo{b.xo_u, (typename Store<STORE>::T *)b.xo_v};
@@ -350,6 +408,28 @@ static void launch_tiled_t(const SolveBufs &b, const Dims &d, const Coef &cf, in
 }
 
 bool tiled_shape_ok(int ty, int cz) { return (ty == 4 || ty == 8 || ty == 12) && cz >= 1; }
+
+template <int STORE>
+static void launch_batch_t(const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
+                           int ty, int flip, int grid, hipStream_t s) {
+    if (ty == 4)
+        hipLaunchKernelGGL((k_fused_batch<STORE, 4>), dim3(grid), dim3(TX * 7), 0, s, blocks, tiles, ntiles, counters,
+                           cf, flip);
+    else if (ty == 12)
+        hipLaunchKernelGGL((k_fused_batch<STORE, 12>), dim3(grid), dim3(TX * 15), 0, s, blocks, tiles, ntiles,
+                           counters, cf, flip);
+    else
+        hipLaunchKernelGGL((k_fused_batch<STORE, 8>), dim3(grid), dim3(TX * 11), 0, s, blocks, tiles, ntiles,
+                           counters, cf, flip);
+}
+
+void launch_batch(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
+                  int ty, int flip, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters);
+    if (storage == 0) launch_batch_t<0>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
+    else if (storage == 1) launch_batch_t<1>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
+    else launch_batch_t<2>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
+}
 
 bool tiled_fits(const Dims &d) {
     // every byte offset (component * n + plane * nx * ny, in 4-byte elements) must fit a signed 32-bit offset
