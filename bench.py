@@ -58,7 +58,7 @@ def cpu_baseline(scene, bins_centers, iters_sample: int = 150, crop: int = 64, n
     # a crop block around mid-height, where the surface is
     import scenes
     o = g.origin.astype(np.float64)
-    z0 = nz // 2 - crop // 2
+    z0 = max(0, nz // 2 - crop // 2)
     cg = scenes.Grid(np.array([o[0], o[1], o[2] + z0 * g.h], dtype=np.float32), g.h, (crop, crop, crop), 0)
     csc = scenes.Scene(scene.depth, scene.cams, cg)
     hcrop, _ = oracle.histograms(csc, pyr)
@@ -78,9 +78,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="terrain256",
+                    choices=["terrain256", "sphere32", "city_batch", "city_serve", "city_precision"])
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--iters", type=int, default=1000)
+    ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--blocks", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--arrivals", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", action="store_true", help="skip the per-kernel roofline timing")
     args = ap.parse_args()
@@ -88,7 +93,21 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "city_batch":
+        return bench_city_batch(args)
+    if args.workload == "city_serve":
+        from bench_serve import bench_city_serve
+        return bench_city_serve(args)
+    if args.workload == "city_precision":
+        from bench_precision import bench_city_precision
+        return bench_city_precision(args)
+    if args.iters is None:
+        args.iters = 300 if args.workload == "sphere32" else 1000
+    return bench_block(args)
 
+
+def bench_block(args):
+    """One block: terrain256 (the default) or sphere32."""
     import torch
     import paper_2107_14790_amd as tgv
     import scenes
@@ -98,9 +117,14 @@ def main():
     storage = tgv.STORAGE_NAMES[args.storage]
     n = args.n
     n_side = 8
-    log(f"generating terrain scene n={n}, {n_side * n_side} cameras 1024x1024")
     t0 = time.perf_counter()
-    sc = scenes.terrain_scene(n=n, n_side=n_side, W=1024, H=1024, f=1536.0, device="cuda")
+    if args.workload == "sphere32":
+        n = 32
+        log("generating sphere scene 32^3, 8 cameras 128x128")
+        sc = scenes.sphere_scene()
+    else:
+        log(f"generating terrain scene n={n}, {n_side * n_side} cameras 1024x1024")
+        sc = scenes.terrain_scene(n=n, n_side=n_side, W=1024, H=1024, f=1536.0, device="cuda")
     log(f"scene ready in {time.perf_counter() - t0:.1f} s")
     H, W = sc.depth.shape[1:]
     depth = torch.from_numpy(sc.depth).to(dev)
@@ -151,7 +175,7 @@ def main():
     pyr_ms, hist_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     roof = None
     if not args.kernel_only:
-        it_hi, it_lo = 400, 200
+        it_hi, it_lo = (400, 200) if n >= 128 else (2000, 1000)
         times = {}
         for its in (it_lo, it_hi, it_lo, it_hi):
             u.zero_()
@@ -174,7 +198,7 @@ def main():
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
-        cpu = cpu_baseline(sc, bins.centers32())
+        cpu = cpu_baseline(sc, bins.centers32(), crop=min(64, n), iters_sample=150 if n >= 64 else 600)
         cpu.pop("hist_pairs_per_s", None)
 
     lat_ms = sorted(1000.0 * x for x in lat)
@@ -191,7 +215,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if storage == 0 else ("f32 compute, " + args.storage + " storage"),
         "data": "synthetic",
-        "config": {"workload": f"terrain{n}", "grid": [g.nx, g.ny, g.nz], "cameras": len(sc.cams),
+        "config": {"workload": args.workload if args.workload != "terrain256" else f"terrain{n}",
+                   "grid": [g.nx, g.ny, g.nz], "cameras": len(sc.cams),
                    "image": [W, H], "iters": args.iters, "bins": 7, "storage": args.storage,
                    "step": "pyramids + cull + histograms + init + iterations + gap"},
         "roofline": roof,
@@ -202,6 +227,110 @@ def main():
     }
     if rank == 0:
         print(json.dumps(out), flush=True)
+
+
+def bench_city_batch(args):
+    """512 octree-leaf-like blocks of the city (edges log-uniform 32..128 plus a
+    2-voxel halo), 500 iterations each: one batched solve (persistent launch
+    per iteration over all blocks, autotuned tiles, graph replay) against the
+    plain per-block solve of the same blocks; results compared bit for bit."""
+    import torch
+    import paper_2107_14790_amd as tgv
+    from paper_2107_14790_amd.autotune import Autotuner
+    import scenes
+
+    iters = args.iters or 500
+    storage = tgv.STORAGE_NAMES[args.storage]
+    if not os.path.exists(scenes._RAYLIB):
+        scenes.build_raycaster()
+    t0 = time.perf_counter()
+    sc, hf = scenes.city_scene(device="cuda")
+    log(f"city scene: {len(sc.cams)} cameras 1024x1024 in {time.perf_counter() - t0:.1f} s")
+    grids = scenes.city_blocks(sc, n_blocks=args.blocks)
+    ctx = tgv.Context(0)
+    H, W = sc.depth.shape[1:]
+    depth = torch.from_numpy(sc.depth).cuda()
+    cams = tgv.cameras_from(sc.cams)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    pyr = ctx.build_pyramids(depth)
+    e1.record(s)
+    torch.cuda.synchronize()
+    pyr_ms = e0.elapsed_time(e1)
+    del depth
+    hists, states, u0s = [], [], []
+    interior = padded = 0
+    e0.record(s)
+    for g in grids:
+        gc = tgv.grid_from(g)
+        hists.append(ctx.build_histograms(pyr, W, H, cams, gc))
+        nvox = gc.nx * gc.ny * gc.nz
+        padded += nvox
+        interior += (gc.nx - 2 * gc.halo) * (gc.ny - 2 * gc.halo) * (gc.nz - 2 * gc.halo)
+        states.append(tgv.State(ctx, gc, storage))
+        u0s.append(torch.zeros(nvox, device="cuda"))
+    e1.record(s)
+    torch.cuda.synchronize()
+    hist_ms = e0.elapsed_time(e1)
+    log(f"{len(grids)} blocks: {padded / 1e6:.1f} M padded voxels, histograms {hist_ms:.0f} ms")
+    t0 = time.perf_counter()
+    tuner = Autotuner(ctx)
+    tune = tuner.tune(grids, storage)
+    log(f"autotune {time.perf_counter() - t0:.1f} s: tile_y {tune['tile_y']}, classes "
+        + ", ".join(f"{k}:{v['tile_y']}x{v['tile_z']}" for k, v in tune["classes"].items()))
+    params = tgv.Params(iters=iters, storage=storage, tile_y=tune["tile_y"], flags=tgv.FLAG_GRAPH)
+
+    def batched():
+        for st, u0 in zip(states, u0s):
+            st.reset(u0)
+        ctx.solve_batch(states, hists, params, tile_z=tune["tile_z"])
+
+    def plain():
+        for st, u0, h, tz in zip(states, u0s, hists, tune["tile_z"]):
+            st.reset(u0)
+            ctx.solve(st.grid, h, None, tgv.Params(iters=iters, storage=storage, tile_y=tune["tile_y"], tile_z=tz),
+                      state=st)
+
+    batched()  # warm (graph capture)
+    torch.cuda.synchronize()
+    times = {}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        ts = []
+        for _ in range(max(1, args.steps)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        times[name] = ts
+        log(f"{name}: {[round(x, 3) for x in ts]} s")
+        if name == "batched":
+            ref = [st.export()["u"] for st in states[:8]]
+    same = all(torch.equal(a, st.export()["u"]) for a, st in zip(ref, states[:8]))
+    tb, tp = min(times["batched"]), min(times["plain"])
+    bpv = fused_bytes_per_voxel(storage)
+    out = {
+        "metric": METRIC,
+        "value": interior * iters / tb,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1, "steps": len(times["batched"]), "warmup": 1,
+        "ms_per_step": 1000 * tb,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if storage == 0 else "f32 compute, " + args.storage + " storage",
+        "data": "synthetic",
+        "config": {"workload": "city_batch", "blocks": len(grids), "edge": "log-uniform 32..128 + 2 halo",
+                   "iters": iters, "cameras": len(sc.cams), "image": [W, H], "padded_voxels": padded,
+                   "interior_voxels": interior, "tile_y": tune["tile_y"]},
+        "batched": {"s": tb, "blocks_per_s": len(grids) / tb, "updates_per_s_interior": interior * iters / tb,
+                    "algorithmic_GBs": bpv * padded * iters / tb / 1e9},
+        "plain": {"s": tp, "blocks_per_s": len(grids) / tp, "updates_per_s_interior": interior * iters / tp,
+                  "algorithmic_GBs": bpv * padded * iters / tp / 1e9},
+        "speedup_batched_vs_plain": tp / tb,
+        "bitwise_same_alone_and_batched": bool(same),
+        "phases_ms": {"pyramids": pyr_ms, "histograms_all_blocks": hist_ms},
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

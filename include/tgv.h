@@ -177,6 +177,13 @@ tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32_t W, int32
  * u (current and previous iterate), v (same), p, q (double-buffered),
  * held in device memory owned by the state. */
 tgv_status tgv_state_create(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, tgv_state **out);
+/* Same, in caller-owned device memory of at least tgv_state_bytes(grid,
+ * storage) bytes (256-byte aligned); the state never frees it.  Lets a
+ * caller keep states in its own pool (a serving loop, a caching allocator)
+ * without device-synchronising frees. */
+tgv_status tgv_state_wrap(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, void *mem, int64_t bytes,
+                          tgv_state **out);
+/* Release a state (frees its memory unless it was wrapped). */
 void tgv_state_destroy(tgv_state *st);
 /* Device bytes a state of this grid and storage uses. */
 int64_t tgv_state_bytes(const tgv_grid *grid, int32_t storage);

@@ -82,6 +82,8 @@ _SIGS = {
                                             ctypes.c_int32, ctypes.POINTER(GridT), ctypes.POINTER(BinsT), _vp, _vp]),
     "tgv_state_create": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), ctypes.c_int32, ctypes.POINTER(_vp)]),
     "tgv_state_destroy": (None, [_vp]),
+    "tgv_state_wrap": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), ctypes.c_int32, _vp, ctypes.c_int64,
+                                      ctypes.POINTER(_vp)]),
     "tgv_state_bytes": (ctypes.c_int64, [ctypes.POINTER(GridT), ctypes.c_int32]),
     "tgv_state_reset": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "tgv_state_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -362,15 +364,27 @@ class Context:
         return stats_dict(s)
 
 
-class State:
-    """A resumable solver state (device memory owned by libtgv)."""
+def state_bytes(grid, storage: int = STORE_F32) -> int:
+    """Device bytes of a solver state (-1 for an invalid grid)."""
+    g = grid_from(grid)
+    return int(load_library().tgv_state_bytes(ctypes.byref(g), storage))
 
-    def __init__(self, ctx: Context, grid, storage: int = STORE_F32):
+
+class State:
+    """A resumable solver state: device memory owned by libtgv, or a torch
+    tensor given as `memory` (kept alive by this object)."""
+
+    def __init__(self, ctx: Context, grid, storage: int = STORE_F32, memory: torch.Tensor = None):
         self.ctx = ctx
         self.grid = grid_from(grid)
         self.storage = storage
+        self.memory = memory
         h = _vp()
-        ctx._check(ctx.lib.tgv_state_create(ctx.h, ctypes.byref(self.grid), storage, ctypes.byref(h)))
+        if memory is None:
+            ctx._check(ctx.lib.tgv_state_create(ctx.h, ctypes.byref(self.grid), storage, ctypes.byref(h)))
+        else:
+            ctx._check(ctx.lib.tgv_state_wrap(ctx.h, ctypes.byref(self.grid), storage, _ptr(memory),
+                                              memory.numel() * memory.element_size(), ctypes.byref(h)))
         self.h = h
         self.n = self.grid.nx * self.grid.ny * self.grid.nz
 

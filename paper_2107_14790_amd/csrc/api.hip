@@ -340,23 +340,8 @@ extern "C" int64_t tgv_state_bytes(const tgv_grid *grid, int32_t storage) {
     return 2 * align256(4 * n) + 2 * align256(3 * n * sb) + 2 * align256(3 * n * sb) + 2 * align256(6 * n * sb);
 }
 
-extern "C" tgv_status tgv_state_create(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, tgv_state **out) {
-    if (!ctx || !out) return TGV_E_INVAL;
-    *out = nullptr;
-    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_state_create: bad grid");
-    if (storage < 0 || storage > 2) return fail(ctx, TGV_E_INVAL, "tgv_state_create: bad storage %d", storage);
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    tgv_state *st = new tgv_state();
-    st->grid = *grid;
-    st->storage = storage;
-    st->n = (long long)grid->nx * grid->ny * grid->nz;
-    long long bytes = tgv_state_bytes(grid, storage);
-    if (hipMalloc(&st->mem, bytes) != hipSuccess) {
-        delete st;
-        (void)hipGetLastError();
-        return fail(ctx, TGV_E_NOMEM, "tgv_state_create: cannot allocate %lld bytes", bytes);
-    }
-    long long sb = storage_bytes(storage), n = st->n;
+static void state_layout(tgv_state *st) {
+    long long sb = storage_bytes(st->storage), n = st->n;
     char *b = (char *)st->mem;
     for (int k = 0; k < 2; k++) {
         st->u[k] = (float *)b;
@@ -378,13 +363,54 @@ extern "C" tgv_status tgv_state_create(tgv_ctx *ctx, const tgv_grid *grid, int32
     st->yc = 0;
     st->fresh = true;
     st->iters_done = 0;
+}
+
+extern "C" tgv_status tgv_state_create(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, tgv_state **out) {
+    if (!ctx || !out) return TGV_E_INVAL;
+    *out = nullptr;
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_state_create: bad grid");
+    if (storage < 0 || storage > 2) return fail(ctx, TGV_E_INVAL, "tgv_state_create: bad storage %d", storage);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    tgv_state *st = new tgv_state();
+    st->grid = *grid;
+    st->storage = storage;
+    st->n = (long long)grid->nx * grid->ny * grid->nz;
+    st->owned = true;
+    long long bytes = tgv_state_bytes(grid, storage);
+    if (hipMalloc(&st->mem, bytes) != hipSuccess) {
+        delete st;
+        (void)hipGetLastError();
+        return fail(ctx, TGV_E_NOMEM, "tgv_state_create: cannot allocate %lld bytes", bytes);
+    }
+    state_layout(st);
+    *out = st;
+    return TGV_OK;
+}
+
+extern "C" tgv_status tgv_state_wrap(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, void *mem, int64_t bytes,
+                                     tgv_state **out) {
+    if (!ctx || !out) return TGV_E_INVAL;
+    *out = nullptr;
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_state_wrap: bad grid");
+    if (storage < 0 || storage > 2) return fail(ctx, TGV_E_INVAL, "tgv_state_wrap: bad storage %d", storage);
+    if (!mem || ((uintptr_t)mem & 255)) return fail(ctx, TGV_E_INVAL, "tgv_state_wrap: memory not 256-byte aligned");
+    if (bytes < tgv_state_bytes(grid, storage))
+        return fail(ctx, TGV_E_INVAL, "tgv_state_wrap: %lld bytes < %lld needed", (long long)bytes,
+                    (long long)tgv_state_bytes(grid, storage));
+    tgv_state *st = new tgv_state();
+    st->grid = *grid;
+    st->storage = storage;
+    st->n = (long long)grid->nx * grid->ny * grid->nz;
+    st->owned = false;
+    st->mem = mem;
+    state_layout(st);
     *out = st;
     return TGV_OK;
 }
 
 extern "C" void tgv_state_destroy(tgv_state *st) {
     if (!st) return;
-    (void)hipFree(st->mem);
+    if (st->owned) (void)hipFree(st->mem);
     delete st;
 }
 

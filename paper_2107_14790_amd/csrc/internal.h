@@ -122,6 +122,7 @@ struct tgv_state {
     tgv_grid grid;
     int storage;
     void *mem;              // one allocation holding every field
+    bool owned;             // false: caller-owned memory (tgv_state_wrap)
     long long n;
     float *u[2];
     void *v[2];
