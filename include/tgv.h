@@ -232,6 +232,18 @@ tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const *states, co
                            const tgv_bins *bins, const tgv_params *params, const int32_t *tile_z_host,
                            tgv_stats *stats_host, void *stream);
 
+/* ---- zero level (Sec. 4.6) ------------------------------------------ */
+
+/* Iso-surface points of u = 0 on a block: for every grid edge between
+ * voxel x and x + e_i whose values have different signs (u > 0 against
+ * u <= 0), the point origin + (x + 1/2 + t e_i) h with t = u(x) / (u(x) -
+ * u(x + e_i)), written as 4 floats (X, Y, Z, i) to points[k], in voxel
+ * order then axis order (deterministic).  At most max_points are written
+ * (points may be NULL with max_points 0 to only count); *count_host
+ * receives the total number of crossings.  Synchronises the stream. */
+tgv_status tgv_extract_crossings(tgv_ctx *ctx, const tgv_grid *grid, const float *u, float *points,
+                                 int64_t max_points, int64_t *count_host, void *stream);
+
 /* Energy statistics of a state (synchronises the stream). */
 tgv_status tgv_energy(tgv_ctx *ctx, const tgv_state *st, const uint16_t *hist, const tgv_bins *bins,
                       const tgv_params *params, tgv_stats *stats_host, void *stream);

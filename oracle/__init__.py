@@ -295,3 +295,36 @@ def weighted_median_interval(hk, ck):
         m = float(expanded[W // 2])
         return m, m
     return float(expanded[W // 2 - 1]), float(expanded[W // 2])
+
+
+# ----------------------------------------------------------------------------
+# zero level (Sec. 4.6)
+# ----------------------------------------------------------------------------
+def crossings(u, shape, origin, h) -> np.ndarray:
+    """Iso-surface points of u = 0: on every grid edge (x, x + e_i) whose end
+    values have different signs (u > 0 against u <= 0), the point
+    origin + (x + 1/2 + t e_i) h with t = u(x) / (u(x) - u(x + e_i)).
+    Binary32 arithmetic in the order written; rows (X, Y, Z, i) in voxel
+    order, then axis order."""
+    nx, ny, nz = shape
+    f = np.float32
+    U = np.asarray(u, dtype=np.float32).reshape(nz, ny, nx)
+    o = np.asarray(origin, dtype=np.float32)
+    h = f(h)
+    rows = []
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                a = U[z, y, x]
+                c = [o[0] + (f(x) + f(0.5)) * h, o[1] + (f(y) + f(0.5)) * h, o[2] + (f(z) + f(0.5)) * h]
+                nb = [(x + 1 < nx, (z, y, x + 1)), (y + 1 < ny, (z, y + 1, x)), (z + 1 < nz, (z + 1, y, x))]
+                for i, (ok, j) in enumerate(nb):
+                    if not ok:
+                        continue
+                    b = U[j]
+                    if (a > 0) != (b > 0):
+                        t = f(a / f(a - b))
+                        p = list(c)
+                        p[i] = f(c[i] + f(t * h))
+                        rows.append([p[0], p[1], p[2], f(i)])
+    return np.array(rows, dtype=np.float32).reshape(-1, 4)

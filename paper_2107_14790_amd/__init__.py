@@ -92,6 +92,8 @@ _SIGS = {
                                  _vp, _vp, ctypes.POINTER(StatsT), _vp]),
     "tgv_energy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT),
                                   ctypes.POINTER(StatsT), _vp]),
+    "tgv_extract_crossings": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, _vp, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int64), _vp]),
     "tgv_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                        ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(StatsT), _vp]),
@@ -353,6 +355,17 @@ class Context:
         self._check(self.lib.tgv_solve_batch(self.h, n, sarr, harr, ctypes.byref(b), ctypes.byref(p), tz,
                                              st if stats else None, _stream(stream)))
         return [stats_dict(st[i]) for i in range(n)] if stats else None
+
+    def extract_crossings(self, grid, u: torch.Tensor, stream=None) -> torch.Tensor:
+        """Zero-level points of u as a float32 tensor [count, 4] (X, Y, Z, axis)."""
+        g = grid_from(grid)
+        cnt = ctypes.c_int64()
+        self._check(self.lib.tgv_extract_crossings(self.h, ctypes.byref(g), _ptr(u), None, 0, ctypes.byref(cnt),
+                                                   _stream(stream)))
+        out = torch.empty((max(cnt.value, 1), 4), dtype=torch.float32, device=u.device)
+        self._check(self.lib.tgv_extract_crossings(self.h, ctypes.byref(g), _ptr(u), _ptr(out), cnt.value,
+                                                   ctypes.byref(cnt), _stream(stream)))
+        return out[:cnt.value]
 
     def energy(self, state: "State", hist: torch.Tensor, params: Params = None, bins: Bins = None,
                stream=None) -> dict:

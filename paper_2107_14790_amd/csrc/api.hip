@@ -148,7 +148,11 @@ extern "C" tgv_status tgv_create(int device, tgv_ctx **out) {
     c->graph_exec = nullptr;
     c->graph_key.clear();
     c->side = nullptr;
-    if (hipEventCreateWithFlags(&c->cams_evt, hipEventDisableTiming) != hipSuccess ||
+    c->ext_scratch = nullptr;
+    c->ext_cap = 0;
+    c->ext_total_host = nullptr;
+    if (hipHostMalloc((void **)&c->ext_total_host, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->cams_evt, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->bt_evt, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming) != hipSuccess ||
@@ -184,6 +188,8 @@ extern "C" void tgv_destroy(tgv_ctx *c) {
     (void)hipFree(c->bt_tiles_dev);
     (void)hipHostFree(c->bt_blocks_host);
     (void)hipHostFree(c->bt_tiles_host);
+    (void)hipFree(c->ext_scratch);
+    (void)hipHostFree(c->ext_total_host);
     delete c;
 }
 
@@ -781,5 +787,40 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             r = run_energy(ctx, states[i], hist[i], bins, params, &stats_host[i], s);
             if (r != TGV_OK) return r;
         }
+    return TGV_OK;
+}
+
+
+// ===========================================================================
+// zero-level crossings
+// ===========================================================================
+extern "C" tgv_status tgv_extract_crossings(tgv_ctx *ctx, const tgv_grid *grid, const float *u, float *points,
+                                            int64_t max_points, int64_t *count_host, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_extract_crossings: bad grid");
+    if (!u || !count_host || max_points < 0 || (max_points > 0 && !points))
+        return fail(ctx, TGV_E_INVAL, "tgv_extract_crossings: bad arguments");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = S(stream);
+    Dims d = make_dims(*grid);
+    long long nb = extract_blocks(d);
+    long long need = align256(4 * nb) + 8 * (nb + 1);
+    if (need > ctx->ext_cap) {
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        (void)hipFree(ctx->ext_scratch);
+        ctx->ext_scratch = nullptr;
+        ctx->ext_cap = 0;
+        HIP_TRY(ctx, hipMalloc(&ctx->ext_scratch, need));
+        ctx->ext_cap = need;
+    }
+    unsigned *counts = (unsigned *)ctx->ext_scratch;
+    unsigned long long *offsets = (unsigned long long *)((char *)ctx->ext_scratch + align256(4 * nb));
+    launch_extract(u, d, *grid, counts, offsets, (float4 *)points, max_points, s);
+    tgv_status r = check_launch(ctx, "extract crossings");
+    if (r != TGV_OK) return r;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->ext_total_host, offsets + nb, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    *count_host = (int64_t)*ctx->ext_total_host;
     return TGV_OK;
 }

@@ -88,6 +88,9 @@ void launch_fill_bytes0(void *p, long long nbytes, hipStream_t s);
 void launch_convert(const void *src, int src_storage, void *dst, int dst_storage, long long n, hipStream_t s);
 
 PyrGeom pyr_geom(int W, int H);
+int extract_blocks(const Dims &d);
+void launch_extract(const float *u, const Dims &d, const tgv_grid &g, unsigned *counts, unsigned long long *offsets,
+                    float4 *pts, long long max_points, hipStream_t s);
 
 }  // namespace tgv
 
@@ -116,6 +119,10 @@ struct tgv_ctx {
     std::string graph_key;
     hipStream_t side;
     hipEvent_t ev_a, ev_b;
+    // crossing extraction scratch
+    void *ext_scratch;
+    long long ext_cap;
+    unsigned long long *ext_total_host;
 };
 
 struct tgv_state {

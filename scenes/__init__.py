@@ -154,8 +154,12 @@ def camera_z_range(cams: Cameras, k: int, grid: Grid) -> tuple:
 def add_noise(depth64: np.ndarray, cams: Cameras, grid: Grid, sigma: float, outlier_frac: float,
               rng: np.random.Generator) -> np.ndarray:
     """Gaussian z-noise then uniform outliers on valid pixels; returns float32 maps."""
+    import sys
     out = np.zeros(depth64.shape, dtype=np.float32)
+    big = depth64.size > (1 << 28)
     for k in range(depth64.shape[0]):
+        if big and k % 32 == 0:
+            print(f"[scenes] noise {k}/{depth64.shape[0]}", file=sys.stderr, flush=True)
         d = depth64[k].copy()
         valid = d > 0
         if sigma > 0:

@@ -332,3 +332,38 @@ def test_tiled_kernel_bitwise_equals_split(ctx, shape, halo, storage):
                           tgv.Params(iters=23, storage=storage, tile_y=ty, tile_z=cz))
         for k in ref:
             assert np.array_equal(ref[k].view(np.uint32), got[k].view(np.uint32)), (k, ty, cz)
+
+
+# ---------------------------------------------------------------------------
+# zero-level points
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(37, 29, 23), (64, 8, 9), (1, 1, 1), (300, 3, 2)])
+def test_crossings_bit_exact(ctx, shape):
+    say("crossings", shape)
+    rng = np.random.default_rng(sum(shape))
+    n = int(np.prod(shape))
+    u = rng.uniform(-1, 1, n).astype(np.float32)
+    u[rng.random(n) < 0.1] = 0.0
+    origin = np.array([-0.3, 0.1, 2.0], dtype=np.float32)
+    h = 0.0625
+    import paper_2107_14790_amd as tgv
+    g = tgv.grid_c(origin, h, shape, 0)
+    pts = ctx.extract_crossings(g, torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = oracle.crossings(u, shape, origin, h)
+    assert pts.shape == ref.shape
+    assert np.array_equal(pts.view(np.uint32), ref.view(np.uint32))
+
+
+def test_crossings_of_solved_sphere(ctx):
+    say("sphere crossings")
+    sc = scenes.sphere_scene()
+    ref_h, _ = oracle.histograms(sc)
+    u, _ = solve_gpu(ctx, ref_h, (32, 32, 32), 300)
+    u32 = u.astype(np.float32)
+    import paper_2107_14790_amd as tgv
+    g = tgv.grid_from(sc.grid)
+    pts = ctx.extract_crossings(g, torch.from_numpy(u32).cuda()).cpu().numpy()
+    ref = oracle.crossings(u32, (32, 32, 32), sc.grid.origin, sc.grid.h)
+    assert np.array_equal(pts.view(np.uint32), ref.view(np.uint32))
+    r = np.linalg.norm(pts[:, :3], axis=1)
+    assert len(pts) > 1000 and np.median(np.abs(r - 1.0)) < 0.05  # the surface is the unit sphere

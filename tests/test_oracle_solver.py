@@ -335,3 +335,32 @@ def test_weak_duality_random_feasible_points():
         P, _ = oracle.primal_energy(hist, shape, C7, u, v)
         D = oracle.dual_energy(hist, shape, C7, u, p, q)
         assert D <= P + 1e-9
+
+
+# ---------------------------------------------------------------------------
+# zero-level points (Sec. 4.6)
+# ---------------------------------------------------------------------------
+def test_crossings_of_a_linear_field_lie_on_its_plane():
+    nx, ny, nz = 7, 6, 5
+    h = 0.5
+    origin = np.array([-1.0, 2.0, 0.0], dtype=np.float32)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    # u = 0 on the plane x + 2y - z = 4.25 (voxel units)
+    u = (x + 2 * y - z - 4.25).astype(np.float32) / 8
+    pts = oracle.crossings(u.ravel(), (nx, ny, nz), origin, h)
+    assert len(pts) > 0
+    vx = (pts[:, :3] - origin) / h - 0.5  # back to voxel units
+    np.testing.assert_allclose(vx[:, 0] + 2 * vx[:, 1] - vx[:, 2], 4.25, atol=1e-5)
+    # the number of sign-changing edges, counted independently
+    pos = u > 0
+    n_edges = ((pos[:, :, 1:] != pos[:, :, :-1]).sum() + (pos[:, 1:, :] != pos[:, :-1, :]).sum()
+               + (pos[1:] != pos[:-1]).sum())
+    assert len(pts) == n_edges
+
+
+def test_no_crossings_in_a_constant_sign_field():
+    u = np.full(4 * 4 * 4, 0.3, dtype=np.float32)
+    assert len(oracle.crossings(u, (4, 4, 4), (0, 0, 0), 1.0)) == 0
+    u[21] = 0.0  # voxel (1, 1, 1): u <= 0 counts as inside; its six edges change sign
+    pts = oracle.crossings(u, (4, 4, 4), (0, 0, 0), 1.0)
+    assert len(pts) == 6 and np.all(pts[:, 3] >= 0)
