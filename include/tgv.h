@@ -232,6 +232,26 @@ tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const *states, co
                            const tgv_bins *bins, const tgv_params *params, const int32_t *tile_z_host,
                            tgv_stats *stats_host, void *stream);
 
+/* ---- coarse-to-fine (Sec. 3.2, Sec. 4.5) ------------------------------ */
+
+/* Nearest-parent prolongation: u_fine(i, j, k) = u_coarse(i/2, j/2, k/2)
+ * (integer division) for every fine voxel; the coarse grid must have
+ * ceil(n/2) voxels per axis.  The indicator of a cube's parent is what the
+ * paper freezes on a part's border and starts the finer level from. */
+tgv_status tgv_prolongate(tgv_ctx *ctx, const tgv_grid *coarse, const float *u_coarse, const tgv_grid *fine,
+                          float *u_fine, void *stream);
+
+/* Coarse-to-fine solve of one block: levels k = levels-1 .. 0 with voxel
+ * size h 2^k and ceil(n / 2^k) voxels per axis over the same origin (the
+ * band width delta scales with the voxel, Sec. 3.1); each level builds its
+ * histograms from the pyramids, starts from the prolongated coarser
+ * solution (0 on the coarsest), keeps u frozen on its halo (the finest
+ * level uses grid->halo, coarser levels none) and runs params->iters
+ * iterations.  The finest u is written to u_out.  Synchronises. */
+tgv_status tgv_solve_coarse_to_fine(tgv_ctx *ctx, const float *pyr, int32_t W, int32_t H, const tgv_camera *cams_host,
+                                    int32_t n_cams, const tgv_grid *grid, const tgv_bins *bins,
+                                    const tgv_params *params, int32_t levels, float *u_out, void *stream);
+
 /* ---- zero level (Sec. 4.6) ------------------------------------------ */
 
 /* Iso-surface points of u = 0 on a block: for every grid edge between

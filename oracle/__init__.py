@@ -328,3 +328,62 @@ def crossings(u, shape, origin, h) -> np.ndarray:
                         p[i] = f(c[i] + f(t * h))
                         rows.append([p[0], p[1], p[2], f(i)])
     return np.array(rows, dtype=np.float32).reshape(-1, 4)
+
+
+# ----------------------------------------------------------------------------
+# coarse-to-fine (Sec. 3.2, Sec. 4.5)
+# ----------------------------------------------------------------------------
+class _Grid:
+    def __init__(self, origin, h, n, halo=0):
+        self.origin = np.asarray(origin, dtype=np.float32)
+        self.h = float(np.float32(h))
+        self.n = tuple(int(v) for v in n)
+        self.halo = int(halo)
+
+    @property
+    def nvox(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+
+class _Scene:
+    def __init__(self, depth, cams, grid):
+        self.depth, self.cams, self.grid = depth, cams, grid
+
+
+def prolongate(u_coarse, coarse_shape, fine_shape) -> np.ndarray:
+    """Each fine voxel takes the value of its parent cube: u_f(i, j, k) =
+    u_c(i // 2, j // 2, k // 2) (the paper freezes a part's border to the
+    parent level's indicator and refines from it)."""
+    cx, cy, cz = coarse_shape
+    fx, fy, fz = fine_shape
+    U = np.asarray(u_coarse).reshape(cz, cy, cx)
+    k, j, i = np.meshgrid(np.arange(fz) // 2, np.arange(fy) // 2, np.arange(fx) // 2, indexing="ij")
+    return U[k, j, i].ravel()
+
+
+def coarse_to_fine(scene, levels, iters, alpha0=2.0, alpha1=1.0, lam=1.0, tau=None, sigma=None, num_bins=7,
+                   rule=0, centers=None):
+    """Solve the block on levels-1 .. 0 with voxel size h 2^k (ceil(n / 2^k)
+    voxels per axis, same origin, delta scaled with the voxel): each level's
+    histograms come from the depth maps, its start value is the prolongated
+    coarser solution (0 on the coarsest) and its border layer (the finest
+    level's halo; none on coarser levels) stays frozen."""
+    g0 = scene.grid
+    grids = [_Grid(g0.origin, g0.h, g0.n, g0.halo)]
+    for k in range(1, levels):
+        p = grids[-1]
+        grids.append(_Grid(p.origin, np.float32(p.h) * np.float32(2.0), tuple((v + 1) // 2 for v in p.n), 0))
+    delta0 = np.float32(3.0) * np.float32(g0.h)
+    if centers is None:
+        centers = np.full(8, np.inf, dtype=np.float32)
+        centers[:num_bins] = np.linspace(-1.0, 1.0, num_bins).astype(np.float32)
+    pyr = pyramids(scene.depth)
+    u = None
+    for k in range(levels - 1, -1, -1):
+        gk = grids[k]
+        hk, _ = histograms(_Scene(scene.depth, scene.cams, gk), pyr, num_bins=num_bins, rule=rule,
+                           delta=float(delta0 * np.float32(2 ** k)))
+        u0 = np.zeros(gk.nvox) if u is None else prolongate(u, grids[k + 1].n, gk.n)
+        st = solve(hk, gk.n, centers, iters, alpha0, alpha1, lam, tau, sigma, halo=gk.halo, num_bins=num_bins, u0=u0)
+        u = st.u
+    return u

@@ -94,6 +94,10 @@ _SIGS = {
                                   ctypes.POINTER(StatsT), _vp]),
     "tgv_extract_crossings": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, _vp, ctypes.c_int64,
                                              ctypes.POINTER(ctypes.c_int64), _vp]),
+    "tgv_prolongate": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, ctypes.POINTER(GridT), _vp, _vp]),
+    "tgv_solve_coarse_to_fine": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Camera),
+                                                ctypes.c_int32, ctypes.POINTER(GridT), ctypes.POINTER(BinsT),
+                                                ctypes.POINTER(ParamsT), ctypes.c_int32, _vp, _vp]),
     "tgv_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                        ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(StatsT), _vp]),
@@ -355,6 +359,27 @@ class Context:
         self._check(self.lib.tgv_solve_batch(self.h, n, sarr, harr, ctypes.byref(b), ctypes.byref(p), tz,
                                              st if stats else None, _stream(stream)))
         return [stats_dict(st[i]) for i in range(n)] if stats else None
+
+    def prolongate(self, coarse, u_coarse: torch.Tensor, fine, out: torch.Tensor = None, stream=None):
+        gc, gf = grid_from(coarse), grid_from(fine)
+        if out is None:
+            out = torch.empty(gf.nx * gf.ny * gf.nz, dtype=torch.float32, device=u_coarse.device)
+        self._check(self.lib.tgv_prolongate(self.h, ctypes.byref(gc), _ptr(u_coarse), ctypes.byref(gf), _ptr(out),
+                                            _stream(stream)))
+        return out
+
+    def solve_coarse_to_fine(self, pyr: torch.Tensor, W: int, H: int, cams, grid, levels: int,
+                             params: Params = None, bins: Bins = None, stream=None) -> torch.Tensor:
+        """Coarse-to-fine solve of one block; returns the finest u."""
+        g = grid_from(grid)
+        b = (bins or Bins()).to_c(g.h)
+        p = (params or Params(iters=200)).to_c()
+        arr, n = cameras_from(cams)
+        out = torch.empty(g.nx * g.ny * g.nz, dtype=torch.float32, device=pyr.device)
+        self._check(self.lib.tgv_solve_coarse_to_fine(self.h, _ptr(pyr), W, H, arr, n, ctypes.byref(g),
+                                                      ctypes.byref(b), ctypes.byref(p), int(levels), _ptr(out),
+                                                      _stream(stream)))
+        return out
 
     def extract_crossings(self, grid, u: torch.Tensor, stream=None) -> torch.Tensor:
         """Zero-level points of u as a float32 tensor [count, 4] (X, Y, Z, axis)."""

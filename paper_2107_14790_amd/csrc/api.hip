@@ -824,3 +824,68 @@ extern "C" tgv_status tgv_extract_crossings(tgv_ctx *ctx, const tgv_grid *grid, 
     *count_host = (int64_t)*ctx->ext_total_host;
     return TGV_OK;
 }
+
+
+// ===========================================================================
+// coarse-to-fine
+// ===========================================================================
+extern "C" tgv_status tgv_prolongate(tgv_ctx *ctx, const tgv_grid *coarse, const float *u_coarse, const tgv_grid *fine,
+                                     float *u_fine, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!grid_ok(coarse) || !grid_ok(fine) || !u_coarse || !u_fine)
+        return fail(ctx, TGV_E_INVAL, "tgv_prolongate: bad arguments");
+    if (coarse->nx != (fine->nx + 1) / 2 || coarse->ny != (fine->ny + 1) / 2 || coarse->nz != (fine->nz + 1) / 2)
+        return fail(ctx, TGV_E_INVAL, "tgv_prolongate: coarse grid must be ceil(n/2) per axis");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_prolongate(u_coarse, make_dims(*coarse), u_fine, make_dims(*fine), S(stream));
+    return check_launch(ctx, "prolongate");
+}
+
+extern "C" tgv_status tgv_solve_coarse_to_fine(tgv_ctx *ctx, const float *pyr, int32_t W, int32_t H,
+                                               const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid,
+                                               const tgv_bins *bins, const tgv_params *params, int32_t levels,
+                                               float *u_out, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!grid_ok(grid) || !bins_ok(bins) || !params_ok(params) || !u_out || levels < 1 || levels > 16)
+        return fail(ctx, TGV_E_INVAL, "tgv_solve_coarse_to_fine: bad arguments");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = S(stream);
+    std::vector<tgv_grid> g(levels);
+    g[0] = *grid;
+    for (int k = 1; k < levels; k++) {
+        g[k] = g[k - 1];
+        g[k].h = g[k - 1].h * 2.0f;
+        g[k].nx = (g[k - 1].nx + 1) / 2;
+        g[k].ny = (g[k - 1].ny + 1) / 2;
+        g[k].nz = (g[k - 1].nz + 1) / 2;
+        g[k].halo = 0;
+    }
+    std::vector<uint16_t *> hist(levels, nullptr);
+    std::vector<float *> u(levels, nullptr);
+    tgv_status r = TGV_OK;
+    for (int k = 0; k < levels && r == TGV_OK; k++) {
+        long long n = (long long)g[k].nx * g[k].ny * g[k].nz;
+        if (hipMalloc((void **)&hist[k], 16 * n) != hipSuccess || hipMalloc((void **)&u[k], 4 * n) != hipSuccess)
+            r = fail(ctx, TGV_E_NOMEM, "tgv_solve_coarse_to_fine: allocation failed");
+    }
+    for (int k = levels - 1; k >= 0 && r == TGV_OK; k--) {
+        tgv_bins bk = *bins;
+        bk.delta = bins->delta * (float)(1 << k);
+        r = tgv_build_histograms(ctx, pyr, W, H, cams_host, n_cams, &g[k], &bk, hist[k], stream);
+        if (r != TGV_OK) break;
+        long long n = (long long)g[k].nx * g[k].ny * g[k].nz;
+        if (k == levels - 1) launch_fill(u[k], 0.0f, n, s);
+        else launch_prolongate(u[k + 1], make_dims(g[k + 1]), u[k], make_dims(g[k]), s);
+        r = tgv_solve(ctx, &g[k], hist[k], &bk, params, u[k], nullptr, nullptr, stream);
+    }
+    if (r == TGV_OK) {
+        hipError_t e = hipMemcpyAsync(u_out, u[0], 4LL * g[0].nx * g[0].ny * g[0].nz, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) r = fail(ctx, TGV_E_DEVICE, "copy: %s", hipGetErrorString(e));
+    }
+    (void)hipStreamSynchronize(s);
+    for (int k = 0; k < levels; k++) {
+        (void)hipFree(hist[k]);
+        (void)hipFree(u[k]);
+    }
+    return r;
+}

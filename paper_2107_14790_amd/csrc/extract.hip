@@ -13,6 +13,8 @@ namespace tgv {
 
 constexpr int EXT_THREADS = 256;
 
+// bit i of the result is set when edge (x, x + e_i) changes sign; t[i] is
+// its crossing parameter (NaN if an end value is NaN)
 __device__ __forceinline__ int crossings_at(const float *__restrict__ u, const Dims &d, long long idx, int x, int y,
                                             int z, float t[3]) {
     const float a = u[idx];
@@ -23,12 +25,12 @@ __device__ __forceinline__ int crossings_at(const float *__restrict__ u, const D
     const long long st[3] = {1, d.sy, d.sz};
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        t[i] = -1.0f;
+        t[i] = 0.0f;
         if (cc[i] < nn[i] - 1) {
             const float b = u[idx + st[i]];
             if ((b > 0.0f) != pa) {
                 t[i] = a / (a - b);
-                c++;
+                c |= 1 << i;
             }
         }
     }
@@ -42,7 +44,7 @@ __global__ void __launch_bounds__(EXT_THREADS) k_count_crossings(const float *__
     if (idx < d.n) {
         const int x = (int)(idx % d.nx), y = (int)((idx / d.nx) % d.ny), z = (int)(idx / d.sz);
         float t[3];
-        c = crossings_at(u, d, idx, x, y, z, t);
+        c = __popc(crossings_at(u, d, idx, x, y, z, t));
     }
     __shared__ unsigned s[EXT_THREADS];
     s[threadIdx.x] = c;
@@ -85,13 +87,14 @@ __global__ void __launch_bounds__(EXT_THREADS) k_write_crossings(const float *__
                                                                  const unsigned long long *__restrict__ offsets,
                                                                  float4 *__restrict__ pts, long long max_points) {
     const long long idx = (long long)blockIdx.x * EXT_THREADS + threadIdx.x;
-    int c = 0, x = 0, y = 0, z = 0;
-    float t[3] = {-1.0f, -1.0f, -1.0f};
+    int c = 0, mask = 0, x = 0, y = 0, z = 0;
+    float t[3] = {0.0f, 0.0f, 0.0f};
     if (idx < d.n) {
         x = (int)(idx % d.nx);
         y = (int)((idx / d.nx) % d.ny);
         z = (int)(idx / d.sz);
-        c = crossings_at(u, d, idx, x, y, z, t);
+        mask = crossings_at(u, d, idx, x, y, z, t);
+        c = __popc(mask);
     }
     __shared__ unsigned s[EXT_THREADS];
     s[threadIdx.x] = c;
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(EXT_THREADS) k_write_crossings(const float *__
     const float cz = g.origin[2] + ((float)z + 0.5f) * g.h;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        if (t[i] >= 0.0f) {
+        if (mask & (1 << i)) {
             if ((long long)k < max_points) {
                 float4 p = make_float4(cx, cy, cz, (float)i);
                 if (i == 0) p.x = cx + t[i] * g.h;
@@ -119,6 +122,19 @@ __global__ void __launch_bounds__(EXT_THREADS) k_write_crossings(const float *__
             k++;
         }
     }
+}
+
+__global__ void k_prolongate(const float *__restrict__ uc, Dims dc, float *__restrict__ uf, Dims df) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= df.nx || y >= df.ny) return;
+    uf[(long long)x + df.sy * y + df.sz * z] = uc[(long long)(x >> 1) + dc.sy * (y >> 1) + dc.sz * (z >> 1)];
+}
+
+void launch_prolongate(const float *uc, const Dims &dc, float *uf, const Dims &df, hipStream_t s) {
+    hipLaunchKernelGGL(k_prolongate, dim3((df.nx + 63) / 64, (df.ny + 3) / 4, df.nz), dim3(64, 4, 1), 0, s, uc, dc, uf,
+                       df);
 }
 
 int extract_blocks(const Dims &d) { return (int)((d.n + EXT_THREADS - 1) / EXT_THREADS); }

@@ -367,3 +367,31 @@ def test_crossings_of_solved_sphere(ctx):
     assert np.array_equal(pts.view(np.uint32), ref.view(np.uint32))
     r = np.linalg.norm(pts[:, :3], axis=1)
     assert len(pts) > 1000 and np.median(np.abs(r - 1.0)) < 0.05  # the surface is the unit sphere
+
+
+# ---------------------------------------------------------------------------
+# coarse-to-fine
+# ---------------------------------------------------------------------------
+def test_prolongate_matches_oracle(ctx):
+    import paper_2107_14790_amd as tgv
+    say("prolongate")
+    rng = np.random.default_rng(4)
+    uc = rng.normal(size=5 * 4 * 3).astype(np.float32)
+    gc = tgv.grid_c((0, 0, 0), 2.0, (5, 4, 3))
+    gf = tgv.grid_c((0, 0, 0), 1.0, (9, 8, 6))
+    out = ctx.prolongate(gc, torch.from_numpy(uc).cuda(), gf).cpu().numpy()
+    assert np.array_equal(out, oracle.prolongate(uc, (5, 4, 3), (9, 8, 6)).astype(np.float32))
+    with pytest.raises(tgv.TgvError):
+        ctx.prolongate(gc, torch.from_numpy(uc).cuda(), tgv.grid_c((0, 0, 0), 1.0, (12, 8, 6)))
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_coarse_to_fine_matches_oracle(ctx, levels):
+    import paper_2107_14790_amd as tgv
+    say("coarse to fine", levels)
+    sc = scenes.sphere_scene(n=32)
+    H, W = sc.depth.shape[1:]
+    pyr = ctx.build_pyramids(torch.from_numpy(sc.depth).cuda())
+    u = ctx.solve_coarse_to_fine(pyr, W, H, sc.cams, sc.grid, levels, tgv.Params(iters=100)).cpu().numpy()
+    ref = oracle.coarse_to_fine(sc, levels, 100)
+    assert np.abs(u.astype(np.float64) - ref).max() <= 1e-4

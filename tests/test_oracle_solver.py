@@ -364,3 +364,20 @@ def test_no_crossings_in_a_constant_sign_field():
     u[21] = 0.0  # voxel (1, 1, 1): u <= 0 counts as inside; its six edges change sign
     pts = oracle.crossings(u, (4, 4, 4), (0, 0, 0), 1.0)
     assert len(pts) == 6 and np.all(pts[:, 3] >= 0)
+
+
+def test_prolongation_takes_the_parent_value():
+    rng = np.random.default_rng(12)
+    uc = rng.normal(size=4 * 3 * 2)
+    uf = oracle.prolongate(uc, (4, 3, 2), (7, 5, 4)).reshape(4, 5, 7)
+    Uc = uc.reshape(2, 3, 4)
+    for (k, j, i) in [(0, 0, 0), (3, 4, 6), (1, 2, 3), (2, 3, 1)]:
+        assert uf[k, j, i] == Uc[k // 2, j // 2, i // 2]
+
+
+def test_one_level_coarse_to_fine_is_the_plain_solve():
+    sc = scenes.sphere_scene(n=12)
+    u1 = oracle.coarse_to_fine(sc, 1, 40)
+    h, _ = oracle.histograms(sc)
+    st = oracle.solve(h, (12, 12, 12), C7, 40)
+    np.testing.assert_array_equal(u1, st.u)
