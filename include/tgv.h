@@ -106,8 +106,11 @@ typedef struct {
     int32_t flags;     /* TGV_FLAG_* */
 } tgv_params;
 
-/* flags: capture a batched solve's iteration loop in a HIP graph and replay it */
-enum { TGV_FLAG_GRAPH = 1 };
+/* flags: TGV_FLAG_GRAPH captures a batched solve's iteration loop in a HIP
+ * graph and replays it; TGV_FLAG_TVL1 solves the TV-L1 model of Eq. 1
+ * (alpha1 |grad u| + lambda data, i.e. v held at 0 and q unused) instead of
+ * the TGV model of Eq. 2. */
+enum { TGV_FLAG_GRAPH = 1, TGV_FLAG_TVL1 = 2 };
 
 /* Energy statistics of a state, reduced in float64:
  *   primal = discrete Eq. 2 at (u, v);

@@ -65,13 +65,13 @@ def lib():
         L.or_prox.argtypes = [c_double, _f64p, _f64p, c_int, c_double, c_double]
         L.or_prox.restype = c_double
         L.or_solve.argtypes = [c_int, c_int, c_int, c_int, _u16p, c_int, _f64p, c_double, c_double, c_double,
-                               c_double, c_double, c_int, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
+                               c_double, c_double, c_int, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, c_int]
         L.or_solve.restype = None
         L.or_primal_energy.argtypes = [c_int, c_int, c_int, c_int, _u16p, c_int, _f64p, c_double, c_double, c_double,
                                        _f64p, _f64p, _f64p]
         L.or_primal_energy.restype = c_double
         L.or_dual_energy.argtypes = [c_int, c_int, c_int, c_int, _u16p, c_int, _f64p, c_double, c_double, _f64p,
-                                     _f64p, _f64p]
+                                     _f64p, _f64p, c_int]
         L.or_dual_energy.restype = c_double
         L.or_norm_K2.argtypes = [c_int, c_int, c_int, c_int, ctypes.c_uint64]
         L.or_norm_K2.restype = c_double
@@ -232,7 +232,7 @@ def centers64(centers, num_bins):
 
 
 def solve(hist, shape, centers, iters, alpha0=2.0, alpha1=1.0, lam=1.0, tau=None, sigma=None, halo=0,
-          num_bins=7, u0=None, state: State = None) -> State:
+          num_bins=7, u0=None, state: State = None, tvl1: bool = False) -> State:
     """Run `iters` primal-dual iterations (fresh start from u0, default 0,
     unless a state is given, which is advanced in place and returned).
     Parameters are rounded to binary32 first, as the GPU library takes them."""
@@ -247,7 +247,7 @@ def solve(hist, shape, centers, iters, alpha0=2.0, alpha1=1.0, lam=1.0, tau=None
     h = np.ascontiguousarray(hist, dtype=np.uint16).reshape(n, 8)
     lib().or_solve(nx, ny, nz, int(halo), h, int(num_bins), centers64(centers, num_bins), f32(alpha0), f32(alpha1),
                    f32(lam), f32(tau), f32(sigma), int(iters), state.u, state.v, state.p, state.q, state.ubar,
-                   state.vbar)
+                   state.vbar, int(bool(tvl1)))
     return state
 
 
@@ -264,18 +264,18 @@ def primal_energy(hist, shape, centers, u, v, alpha0=2.0, alpha1=1.0, lam=1.0, h
 VBOUND = 2.0 * np.sqrt(3.0)
 
 
-def dual_energy(hist, shape, centers, u, p, q, lam=1.0, halo=0, num_bins=7, vbound=VBOUND):
+def dual_energy(hist, shape, centers, u, p, q, lam=1.0, halo=0, num_bins=7, vbound=VBOUND, tvl1=False):
     nx, ny, nz = shape
     n = nx * ny * nz
     return float(lib().or_dual_energy(nx, ny, nz, int(halo), np.ascontiguousarray(hist, dtype=np.uint16).reshape(n, 8),
                                       int(num_bins), centers64(centers, num_bins), f32(lam), float(vbound),
-                                      _c64(u).ravel(), _c64(p).ravel(), _c64(q).ravel()))
+                                      _c64(u).ravel(), _c64(p).ravel(), _c64(q).ravel(), int(bool(tvl1))))
 
 
-def gap(hist, shape, centers, st: State, alpha0=2.0, alpha1=1.0, lam=1.0, halo=0, num_bins=7):
+def gap(hist, shape, centers, st: State, alpha0=2.0, alpha1=1.0, lam=1.0, halo=0, num_bins=7, tvl1=False):
     """(P, D, relative gap (P - D) / max(P, 1))."""
     P, _ = primal_energy(hist, shape, centers, st.u, st.v, alpha0, alpha1, lam, halo, num_bins)
-    D = dual_energy(hist, shape, centers, st.u, st.p, st.q, lam, halo, num_bins)
+    D = dual_energy(hist, shape, centers, st.u, st.p, st.q, lam, halo, num_bins, tvl1=tvl1)
     return P, D, (P - D) / max(P, 1.0)
 
 

@@ -394,7 +394,10 @@ static void project(double *y[], int m, const double *wts, long x, double alpha)
         for (int c = 0; c < m; c++) y[c][x] /= s;
 }
 
-/* Primal-dual iterations (first-order primal-dual method with
+/* With tvl1 set the TV-L1 model of Eq. 1 is solved instead: the same
+ * iteration with v held at 0 and no q (K reduces to M.grad).
+ *
+ * Primal-dual iterations (first-order primal-dual method with
  * over-relaxation theta = 1) on the saddle-point form of Eq. 2:
  *   p <- P_{alpha1}(p + sigma K_p(ubar, vbar)),  q <- P_{alpha0}(q + sigma K_q(ubar, vbar));
  *   (gu, gv) = K^T(p, q);
@@ -405,7 +408,7 @@ static void project(double *y[], int m, const double *wts, long x, double alpha)
  * u = ubar = initial u, v = vbar = p = q = 0. */
 void or_solve(int nx, int ny, int nz, int halo, const uint16_t *hist, int nbins, const double *centers,
               double alpha0, double alpha1, double lambda, double tau, double sigma, int iters, double *u,
-              double *v, double *p, double *q, double *ubar, double *vbar)
+              double *v, double *p, double *q, double *ubar, double *vbar, int tvl1)
 {
     dims_t d = mkdims(nx, ny, nz);
     long n = d.n;
@@ -422,6 +425,7 @@ void or_solve(int nx, int ny, int nz, int halo, const uint16_t *hist, int nbins,
             double *pp[3] = {p, p + n, p + 2 * n};
             for (int c = 0; c < 3; c++) p[c * n + x] += sigma * kp[c * n + x];
             project(pp, 3, w3, x, alpha1);
+            if (tvl1) continue; /* TV-L1 (Eq. 1): no second-order dual */
             double *qq[6] = {q, q + n, q + 2 * n, q + 3 * n, q + 4 * n, q + 5 * n};
             for (int c = 0; c < 6; c++) q[c * n + x] += sigma * kq[c * n + x];
             project(qq, 6, w6, x, alpha0);
@@ -439,6 +443,7 @@ void or_solve(int nx, int ny, int nz, int halo, const uint16_t *hist, int nbins,
             }
             ubar[x] = 2.0 * un - u[x];
             u[x] = un;
+            if (tvl1) continue; /* TV-L1: v stays 0 */
             for (int c = 0; c < 3; c++) {
                 double vn = v[c * n + x] - tau * gv[c * n + x];
                 vbar[c * n + x] = 2.0 * vn - v[c * n + x];
@@ -490,9 +495,10 @@ double or_primal_energy(int nx, int ny, int nz, int halo, const uint16_t *hist, 
  *       - vbound sum_x |gv(x)|,   (gu, gv) = K^T(p, q).
  * The inner minimum of a convex piecewise-linear function is attained at
  * a breakpoint or an end, so it is exact over {-1, 1, c_k in [-1, 1]}.
- * D is a lower bound of Eq. 2 over the box (weak duality). */
+ * D is a lower bound of Eq. 2 over the box (weak duality).  For the TV-L1
+ * model (tvl1 set) v is not a variable and its term is absent. */
 double or_dual_energy(int nx, int ny, int nz, int halo, const uint16_t *hist, int nbins, const double *centers,
-                      double lambda, double vbound, const double *u, const double *p, const double *q)
+                      double lambda, double vbound, const double *u, const double *p, const double *q, int tvl1)
 {
     dims_t d = mkdims(nx, ny, nz);
     long n = d.n;
@@ -517,7 +523,7 @@ double or_dual_energy(int nx, int ny, int nz, int halo, const uint16_t *hist, in
             }
             D += best;
         }
-        D -= vbound * sqrt(gv[x] * gv[x] + gv[n + x] * gv[n + x] + gv[2 * n + x] * gv[2 * n + x]);
+        if (!tvl1) D -= vbound * sqrt(gv[x] * gv[x] + gv[n + x] * gv[n + x] + gv[2 * n + x] * gv[2 * n + x]);
     }
     free(gu);
     free(gv);

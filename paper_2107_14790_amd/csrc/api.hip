@@ -72,7 +72,7 @@ bool params_ok(const tgv_params *p) {
     if (p->schedule != TGV_SCHED_FUSED && p->schedule != TGV_SCHED_SPLIT && p->schedule != TGV_SCHED_FUSED_REF)
         return false;
     if (p->tile_y < 0 || p->tile_z < 0) return false;
-    if (p->flags & ~TGV_FLAG_GRAPH) return false;
+    if (p->flags & ~(TGV_FLAG_GRAPH | TGV_FLAG_TVL1)) return false;
     if (p->tile_y != 0 && !tiled_shape_ok(p->tile_y, p->tile_z > 0 ? p->tile_z : 1)) return false;
     return true;
 }
@@ -98,6 +98,7 @@ Coef make_coef(const tgv_params &p, const tgv_bins &b) {
     c.taulam = p.tau * p.lambda;
     c.taulam2 = 2.0f * c.taulam;
     for (int k = 0; k < 8; k++) c.c[k] = k < b.num_bins ? b.centers[k] : INFINITY;
+    c.tvl1 = (p.flags & TGV_FLAG_TVL1) ? 1 : 0;
     return c;
 }
 

@@ -68,6 +68,7 @@ __device__ __forceinline__ bool is_frozen(const Dims &d, int x, int y, int z) {
 struct Coef {
     float alpha0, alpha1, tau, sigma, taulam, taulam2;  // taulam = tau lambda, taulam2 = 2 tau lambda
     float c[8];  // bin centres, +inf in unused slots
+    int tvl1;    // 1: the TV-L1 model of Eq. 1 (v stays 0, q unused)
 };
 
 // ---------------------------------------------------------------------------
@@ -153,6 +154,11 @@ __device__ __forceinline__ float primal_u(float u, const float p[3], const float
 __device__ __forceinline__ void primal_v(float vout[3], const float v[3], const float p[3], const float q[6],
                                          const float qn[3][3], const bool mlo[3], const bool mhi[3],
                                          const Coef &cf) {
+    if (cf.tvl1) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) vout[i] = v[i];
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         float w = mhi[i] ? p[i] : 0.0f;
@@ -186,6 +192,7 @@ __device__ __forceinline__ void dual_pq(float p[3], float q[6], float ub, const 
     p[0] = a;
     p[1] = b;
     p[2] = c;
+    if (cf.tvl1) return;  // no second-order term
     float dm[3][3];  // dm[i][j] = d-_j vbar_i
 #pragma unroll
     for (int i = 0; i < 3; i++)

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(EN_THREADS) k_energy(XBuf<STORE> X, YBuf<STORE
                 }
             }
         }
-        acc[3] += dv - vbound * sqrt(gv2);
+        acc[3] += cf.tvl1 ? dv : dv - vbound * sqrt(gv2);
         acc[4] += fin ? 0.0 : 1.0;
     }
     __shared__ double sh[EN_THREADS / 64][5];

@@ -395,3 +395,25 @@ def test_coarse_to_fine_matches_oracle(ctx, levels):
     u = ctx.solve_coarse_to_fine(pyr, W, H, sc.cams, sc.grid, levels, tgv.Params(iters=100)).cpu().numpy()
     ref = oracle.coarse_to_fine(sc, levels, 100)
     assert np.abs(u.astype(np.float64) - ref).max() <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# TV-L1 model (Eq. 1)
+# ---------------------------------------------------------------------------
+def test_tvl1_matches_oracle(ctx):
+    import paper_2107_14790_amd as tgv
+    say("tv-l1")
+    sc = scenes.sphere_scene()
+    ref_h, _ = oracle.histograms(sc)
+    g = tgv.grid_from(sc.grid)
+    hist = torch.from_numpy(ref_h.view(np.int16)).cuda()
+    st = tgv.State(ctx, g)
+    st.reset(torch.zeros(32 ** 3, device="cuda"))
+    stats = ctx.solve(g, hist, None, tgv.Params(iters=300, flags=tgv.FLAG_TVL1), state=st, stats=True)
+    f = {k: v.cpu().numpy().astype(np.float64) for k, v in st.export().items()}
+    ref = oracle.solve(ref_h, (32, 32, 32), scenes.default_bins(), 300, tvl1=True)
+    assert np.abs(f["u"] - ref.u).max() <= 1e-4
+    assert not f["v"].any() and not f["q"].any()
+    P, D, gr = oracle.gap(ref_h, (32, 32, 32), scenes.default_bins(), ref, tvl1=True)
+    assert abs(stats["primal"] - P) <= 1e-4 * P
+    assert abs(stats["dual"] - D) <= 1e-4 * abs(D) + 1e-3

@@ -381,3 +381,44 @@ def test_one_level_coarse_to_fine_is_the_plain_solve():
     h, _ = oracle.histograms(sc)
     st = oracle.solve(h, (12, 12, 12), C7, 40)
     np.testing.assert_array_equal(u1, st.u)
+
+
+# ---------------------------------------------------------------------------
+# TV-L1 (Eq. 1)
+# ---------------------------------------------------------------------------
+def _tvl1_1d_dp(hist, alpha1, lam):
+    """Exact minimum of lam sum_i sum_k h_ik |u_i - c_k| + alpha1 sum_i |u_{i+1} - u_i|
+    over u in R^N: 1-D TV-L1 with L1 data at the bin centres has a minimiser
+    taking values among the centres, so a Viterbi pass over them is exact."""
+    N = hist.shape[0]
+    c = C64
+    cost = lam * np.array([[np.sum(hist[i, :7] * np.abs(v - c)) for v in c] for i in range(N)])
+    best = cost[0].copy()
+    jump = alpha1 * np.abs(c[:, None] - c[None, :])
+    for i in range(1, N):
+        best = cost[i] + np.min(best[:, None] + jump, axis=0)
+    return float(best.min())
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tvl1_1d_energy_matches_exact_dp(seed):
+    rng = np.random.default_rng(30 + seed)
+    N = 16
+    hist = rand_hist((N, 1, 1), rng, odd=False, lo=0, hi=5)
+    a1, lam = oracle.f32(1.0), oracle.f32(1.0)
+    E = _tvl1_1d_dp(hist, a1, lam)
+    st = oracle.solve(hist, (N, 1, 1), C7, 20000, tvl1=True)
+    assert not st.v.any() and not st.q.any()
+    P, parts = oracle.primal_energy(hist, (N, 1, 1), C7, st.u, st.v)
+    assert parts[1] == 0.0
+    assert P >= E - 1e-9 * max(1.0, E)
+    assert P - E <= 1e-8 * max(1.0, E)
+
+
+def test_tvl1_gap_closes():
+    rng = np.random.default_rng(33)
+    shape = (6, 5, 4)
+    hist = rand_hist(shape, rng, odd=True)
+    st = oracle.solve(hist, shape, C7, 20000, tvl1=True)
+    P, D, g = oracle.gap(hist, shape, C7, st, tvl1=True)
+    assert D <= P + 1e-9 and g < 1e-6
