@@ -635,3 +635,38 @@ def city_blocks(scene: Scene, n_blocks: int = 512, e_min: int = 32, e_max: int =
         origin = (P - 0.5 * n * h).astype(np.float32)
         out.append(Grid(origin, h, (n, n, n), halo))
     return out
+
+
+# ----------------------------------------------------------------------------
+# 360-degree scans (terrestrial LIDAR, Sec. 3.1) as six cube-face depth maps
+# ----------------------------------------------------------------------------
+_CUBE_FACES = [((1.0, 0.0, 0.0), (0.0, 0.0, 1.0)), ((-1.0, 0.0, 0.0), (0.0, 0.0, 1.0)),
+               ((0.0, 1.0, 0.0), (0.0, 0.0, 1.0)), ((0.0, -1.0, 0.0), (0.0, 0.0, 1.0)),
+               ((0.0, 0.0, 1.0), (0.0, 1.0, 0.0)), ((0.0, 0.0, -1.0), (0.0, 1.0, 0.0))]
+
+
+def scan_cameras(center, W: int = 256, vote: int = 5) -> Cameras:
+    """A 360-degree scanner at `center` as six 90-degree pinhole faces
+    (f = W/2, principal point at the centre) covering every direction once;
+    each face casts votes of weight `vote` (5 for near noise-free LIDAR)."""
+    c = np.asarray(center, dtype=np.float64)
+    Rs, ts = [], []
+    for fwd, up in _CUBE_FACES:
+        R, t = look_at(c, c + np.asarray(fwd), up)
+        Rs.append(R)
+        ts.append(t)
+    return make_cameras(Rs, ts, W / 2.0, W / 2.0, W / 2.0, W / 2.0, W, W, vote=vote)
+
+
+def scan_sphere_scene(center=(2.2, 0.4, 0.3), W: int = 128, n: int = 32, extent: float = 1.5, seed: int = 11,
+                      sigma: float = 0.001) -> Scene:
+    """The unit sphere seen by one 360-degree scanner (vote 5, low noise, no
+    outliers) plus, for mixing, the eight ring cameras of sphere_scene."""
+    scan = scan_cameras(center, W)
+    ring = sphere_scene(n=n, extent=extent, sigma=0.0, outlier_frac=0.0)
+    h = np.float32(2.0 * extent / n)
+    grid = Grid(np.full(3, -extent, dtype=np.float32), float(h), (n, n, n), 0)
+    clean = np.stack([sphere_depth(scan, k) for k in range(len(scan))])
+    rng = np.random.default_rng(seed)
+    d_scan = add_noise(clean, scan, grid, sigma, 0.0, rng)
+    return Scene(d_scan, scan, grid, name="scan-sphere")
