@@ -434,3 +434,18 @@ def test_scan_and_stereo_histograms_bit_exact(ctx):
     ref, mx = oracle.histograms(sc)
     assert np.array_equal(hist, ref)
     assert mx >= 5 and hist.max() >= 5
+
+
+def test_histogram_count_limit_exactly_65535(ctx):
+    import paper_2107_14790_amd as tgv
+    say("count limit 65535")
+    sc = scenes.plane_scene(n=(3, 3, 7), z_plane_index=3, n_cams=1)
+    sc.cams.vote[:] = [65535]
+    _, hist = gpu_hist(ctx, sc)
+    ref, mx = oracle.histograms(sc)
+    assert np.array_equal(hist, ref) and mx == 65535 and hist.max() == 65535
+    sc2 = scenes.plane_scene(n=(3, 3, 7), z_plane_index=3, n_cams=2)
+    sc2.cams.vote[:] = [65535, 1]
+    with pytest.raises(tgv.TgvError) as e:
+        gpu_hist(ctx, sc2)
+    assert e.value.status == tgv.TGV_E_OVERFLOW
