@@ -41,29 +41,37 @@ def fused_bytes_per_voxel(storage: int) -> int:
     return state + 16 + state
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tgv_fused_tiled_terrain256_traffic.json")
-KERNEL_SOURCES = ("paper_2107_14790_amd/csrc/solver_tiled.hip", "paper_2107_14790_amd/csrc/device_math.h",
-                  "paper_2107_14790_amd/csrc/fields.h")
+# per kernel: the committed counter summary and the sources it was taken on
+TRAFFIC = {
+    "fused": ("tgv_fused_tiled_terrain256_traffic.json",
+              ("paper_2107_14790_amd/csrc/solver_tiled.hip", "paper_2107_14790_amd/csrc/device_math.h",
+               "paper_2107_14790_amd/csrc/fields.h")),
+    "fused2": ("tgv_fused2_tiled_terrain256_traffic.json",
+               ("paper_2107_14790_amd/csrc/solver_tiled2.hip", "paper_2107_14790_amd/csrc/device_math.h",
+                "paper_2107_14790_amd/csrc/fields.h")),
+}
 
 
-def kernel_sources_hash() -> str:
+def kernel_sources_hash(kernel: str = "fused") -> str:
     import hashlib
     hsh = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in TRAFFIC[kernel][1]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             hsh.update(fh.read())
     return hsh.hexdigest()
 
 
-def measured_traffic(storage: int, tile: str):
-    """HBM bytes per launch of the fused kernel from the committed counter
+def measured_traffic(storage: int, tile: str, kernel: str = "fused"):
+    """HBM bytes per launch of a solver kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
     or None if the kernel sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(ROOT, "profiles", TRAFFIC[kernel][0])
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_sources_sha256") != kernel_sources_hash() or t.get("storage") != storage or t.get("tile") != tile:
+    if (t.get("kernel_sources_sha256") != kernel_sources_hash(kernel) or t.get("storage") != storage
+            or t.get("tile") != tile):
         return None
     return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
 
@@ -110,6 +118,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--schedule", default="fused", choices=["fused", "fused2"],
+                    help="fused: one tiled pass per iteration; fused2: two iterations per pass")
     ap.add_argument("--blocks", type=int, default=512)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--arrivals", type=int, default=300)
@@ -158,7 +168,8 @@ def bench_block(args):
     ctx = tgv.Context(0)
     g = tgv.grid_from(sc.grid)
     bins = tgv.Bins()
-    params = tgv.Params(iters=args.iters, storage=storage)
+    sched = tgv.SCHED_FUSED2 if args.schedule == "fused2" else tgv.SCHED_FUSED
+    params = tgv.Params(iters=args.iters, storage=storage, schedule=sched)
     nvox = g.nx * g.ny * g.nz
     pyr = torch.empty((len(sc.cams), ctx.pyramid_floats(W, H)), dtype=torch.float32, device=dev)
     hist = torch.empty((nvox, 8), dtype=torch.int16, device=dev)
@@ -206,23 +217,29 @@ def bench_block(args):
         times = {}
         for its in (it_lo, it_hi, it_lo, it_hi):
             u.zero_()
-            p2 = tgv.Params(iters=its, storage=storage)
+            p2 = tgv.Params(iters=its, storage=storage, schedule=sched)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
             ctx.solve(g, hist, u, p2, bins)
             e1.record(s)
             torch.cuda.synchronize()
             times.setdefault(its, []).append(e0.elapsed_time(e1))
-        k_ms = (min(times[it_hi]) - min(times[it_lo])) / (it_hi - it_lo)
+        # one launch of the dominant kernel: one iteration (fused) or two (fused2)
+        per_launch = 2 if args.schedule == "fused2" else 1
+        k_ms = (min(times[it_hi]) - min(times[it_lo])) / (it_hi - it_lo) * per_launch
         bpv = fused_bytes_per_voxel(storage)
         achieved = bpv * nvox / (k_ms * 1e-3) / 1e9
-        tile = f"{params.tile_y or 4}x{params.tile_z or 32}"
-        traffic = measured_traffic(storage, tile) if n == 256 else None
+        if args.schedule == "fused2":
+            tile = f"{params.tile_y or 4}x{params.tile_z or 64}"
+        else:
+            tile = f"{params.tile_y or 4}x{params.tile_z or 32}"
+        traffic = measured_traffic(storage, tile, args.schedule) if n == 256 else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, tile=tile,
-                    kernel="tgv fused iteration", bytes_per_voxel=bpv, voxels_per_launch=nvox,
+                    kernel=("tgv fused iteration" if per_launch == 1 else "tgv two fused iterations per pass"),
+                    bytes_per_voxel=bpv, voxels_per_launch=nvox, iterations_per_launch=per_launch,
                     avg_launch_ms=round(k_ms, 5))
-        log(f"fused iteration {k_ms * 1e3:.1f} us -> {achieved:.0f} GB/s algorithmic")
+        log(f"{args.schedule} launch {k_ms * 1e3:.1f} us ({per_launch} iteration(s)) -> {achieved:.0f} GB/s algorithmic")
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -255,6 +272,7 @@ def bench_block(args):
         "config": {"workload": args.workload if args.workload != "terrain256" else f"terrain{n}",
                    "grid": [g.nx, g.ny, g.nz], "cameras": len(sc.cams),
                    "image": [W, H], "iters": args.iters, "bins": 7, "storage": args.storage,
+                   "schedule": args.schedule,
                    "step": "pyramids + cull + histograms + init + iterations + gap"},
         "roofline": roof,
         "cpu_baseline": cpu,

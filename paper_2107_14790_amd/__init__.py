@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtgv.so")
 
 TGV_OK, TGV_E_INVAL, TGV_E_NOMEM, TGV_E_DEVICE, TGV_E_OVERFLOW, TGV_E_UNSUPPORTED = range(6)
 STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
-SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF = 0, 1, 2
+SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF, SCHED_FUSED2 = 0, 1, 2, 3
 FLAG_GRAPH = 1
 FLAG_TVL1 = 2
 STORAGE_NAMES = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}

@@ -69,11 +69,16 @@ bool params_ok(const tgv_params *p) {
     if (!isfinite(p->alpha0) || !isfinite(p->alpha1) || !isfinite(p->lambda)) return false;
     if (p->iters < 0) return false;
     if (p->storage < 0 || p->storage > 2) return false;
-    if (p->schedule != TGV_SCHED_FUSED && p->schedule != TGV_SCHED_SPLIT && p->schedule != TGV_SCHED_FUSED_REF)
+    if (p->schedule != TGV_SCHED_FUSED && p->schedule != TGV_SCHED_SPLIT && p->schedule != TGV_SCHED_FUSED_REF &&
+        p->schedule != TGV_SCHED_FUSED2)
         return false;
     if (p->tile_y < 0 || p->tile_z < 0) return false;
     if (p->flags & ~(TGV_FLAG_GRAPH | TGV_FLAG_TVL1)) return false;
-    if (p->tile_y != 0 && !tiled_shape_ok(p->tile_y, p->tile_z > 0 ? p->tile_z : 1)) return false;
+    if (p->tile_y != 0) {
+        const int cz = p->tile_z > 0 ? p->tile_z : 1;
+        if (p->schedule == TGV_SCHED_FUSED2 ? !tiled2_shape_ok(p->tile_y, cz) : !tiled_shape_ok(p->tile_y, cz))
+            return false;
+    }
     return true;
 }
 
@@ -572,7 +577,21 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
         } else {
             int ty = params->tile_y ? params->tile_y : DEFAULT_TILE_Y;
             int cz = params->tile_z ? params->tile_z : DEFAULT_TILE_Z;
-            for (int it = 0; it + 1 < N; it++) {
+            int it = 0;
+            if (params->schedule == TGV_SCHED_FUSED2 && tiled_fits(d)) {
+                // pairs of fused iterations in one pass; x^{n+1} is never
+                // written, which only the final primal pass could notice,
+                // and it overwrites that buffer
+                const int ty2 = params->tile_y ? params->tile_y : DEFAULT_TILE2_Y;
+                const int cz2 = params->tile_z ? params->tile_z : DEFAULT_TILE2_Z;
+                for (; it + 2 < N; it += 2) {
+                    launch_tiled2(st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, ty2, cz2, s);
+                    st->xc ^= 1;
+                    st->yc ^= 1;
+                }
+                ty = DEFAULT_TILE_Y;
+            }
+            for (; it + 1 < N; it++) {
                 SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
                 if (params->schedule == TGV_SCHED_FUSED_REF) launch_ref(KIND_FUSED, st->storage, b, d, cf, s);
                 else launch_tiled(st->storage, b, d, cf, ty, cz, s);

@@ -71,9 +71,14 @@ int64_t storage_bytes(int storage);
 void launch_ref(int kind, int storage, const SolveBufs &b, const Dims &d, const Coef &cf, hipStream_t s);
 constexpr int DEFAULT_TILE_Y = 4;
 constexpr int DEFAULT_TILE_Z = 32;
+constexpr int DEFAULT_TILE2_Y = 4;
+constexpr int DEFAULT_TILE2_Z = 64;
 bool tiled_shape_ok(int ty, int cz);
 void launch_tiled(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);
 bool tiled_fits(const Dims &d);
+// two fused iterations per launch (temporal blocking), tiles 64 x ty (ty in {4, 6})
+bool tiled2_shape_ok(int ty, int cz);
+void launch_tiled2(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);
 // one fused iteration of every block listed in `tiles` (int4: block, tix | tiy << 16, tiz, 0)
 void launch_batch(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
                   int ty, int flip, int grid, hipStream_t s);

@@ -1,0 +1,378 @@
+// Two fused iterations per pass over HBM (temporal blocking along z).
+//
+// A workgroup owns a 64 x TY column tile and walks a chunk of planes along
+// z, like the one-iteration kernel, but runs two iterations in one sweep:
+//   stage A computes iteration n from the state in memory on the tile and a
+//     one-column ring around it (full update), with the partial primal
+//     updates its dual step needs on a second ring;
+//   stage B computes iteration n+1 on the tile, two planes behind stage A,
+//     from stage A's results held in registers, and writes them to memory.
+// Each input is read from HBM once and each output written once per two
+// iterations.  Stage B needs stage A's results on the tile plus the first
+// ring, stage A needs the state on the tile plus two rings; the rings are
+// carried by five extra waves (two row waves per ring and one for the
+// columns and corners).  Both stages use the per-voxel arithmetic of the
+// one-iteration kernels, so two iterations here are bit-identical to two
+// iterations there.
+#include "fields.h"
+#include "internal.h"
+
+#ifndef TILED2_WAVES_PER_EU
+#define TILED2_WAVES_PER_EU 3
+#endif
+
+namespace tgv {
+
+namespace {
+
+constexpr int TX = 64;
+constexpr unsigned RSRC_WORD3 = 0x00020000u;
+
+__device__ __forceinline__ void lds_barrier2() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc2(const void *p, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, (int)RSRC_WORD3);
+}
+
+template <int STORE>
+struct Io2;
+template <>
+struct Io2<0> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+    }
+};
+template <>
+struct Io2<1> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, 0);
+    }
+};
+template <>
+struct Io2<2> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
+        bf16_t t;
+        Store<2>::st(&t, v);
+        __builtin_amdgcn_raw_buffer_store_b16(t.bits, r, voff, soff, 0);
+    }
+};
+
+// the state of one column at one plane
+struct Pl {
+    float u, v[3], p[3], q[6];
+};
+
+__device__ __forceinline__ int lq2(int slot) { return slot == 0 ? 0 : (slot == 1 ? 1 : slot - 1); }
+
+// LDS exchange planes of one stage over the (TX+4) x (TY+4) index space
+template <int TY>
+struct XLds {
+    static constexpr int EX = TX + 4, NE = EX * (TY + 4);
+    float sPx[NE], sPy[NE];
+    float sQ[5 * NE];
+    float sU[NE];
+    float sV[3 * NE];
+};
+
+// One stage of one column: the z-pipeline of the one-iteration kernel,
+// with its inputs handed in per plane and its dual results handed out.
+struct Stage {
+    bool needU, needV, full, active;  // roles of this column in this stage
+    int z0, zl;                       // output planes of this stage
+    float UP1, UB1, VB2[3];           // u+ and ubar of plane s-1, vbar of plane s-2
+    float VP[3], VB[3], UP, UB;       // this plane step's primal results
+};
+
+}  // namespace
+
+template <int STORE, int TY>
+__global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
+    k_fused2_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn, YBuf<STORE> Yn, const uint16_t *__restrict__ hist,
+                   Dims d, Coef cf, int CZ, int ntx, int nty, int ntz) {
+    using L = XLds<TY>;
+    constexpr int EX = L::EX, NE = L::NE;
+    constexpr int SB = STORE == 0 ? 4 : 2;
+    __shared__ L la, lb;
+
+    const int nb = ntx * nty * ntz;
+    const int per = (nb + 7) / 8;
+    const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (T >= nb) return;
+    const int x0 = (T % ntx) * TX, y0 = ((T / ntx) % nty) * TY, z0 = (T / (ntx * nty)) * CZ;
+    const int zl = min(z0 + CZ, d.nz) - 1;
+
+    // ---- the column this thread owns and its roles in both stages
+    // waves 0..TY-1 core rows; TY: ring-1 row below; TY+1: ring-1 row above;
+    // TY+2: ring-2 row below; TY+3: ring-2 row above; TY+4: the ring
+    // columns, the rows' end columns and the two outer corners
+    const int w = threadIdx.x / TX, lane = threadIdx.x & (TX - 1);
+    int px = -3, py = -3;
+    // kind: 0 core, 1 ring-1, 2 ring-2 needing u+, 3 ring-2 needing v+, 4 ring-2 corner, -1 none
+    int kind = -1;
+    if (w < TY) { px = x0 + lane; py = y0 + w; kind = 0; }
+    else if (w == TY) { px = x0 + lane; py = y0 - 1; kind = 1; }
+    else if (w == TY + 1) { px = x0 + lane; py = y0 + TY; kind = 1; }
+    else if (w == TY + 2) { px = x0 + lane; py = y0 - 2; kind = 3; }
+    else if (w == TY + 3) { px = x0 + lane; py = y0 + TY + 1; kind = 2; }
+    else {
+        int l = lane;
+        if (l < TY) { px = x0 - 1; py = y0 + l; kind = 1; }
+        else if ((l -= TY) < TY) { px = x0 + TX; py = y0 + l; kind = 1; }
+        else if ((l -= TY) < 4) { px = (l & 1) ? x0 + TX : x0 - 1; py = (l & 2) ? y0 + TY : y0 - 1; kind = 1; }
+        else if ((l -= 4) < TY + 2) { px = x0 - 2; py = y0 - 1 + l; kind = 3; }
+        else if ((l -= TY + 2) < TY + 2) { px = x0 + TX + 1; py = y0 - 1 + l; kind = 2; }
+        else if ((l -= TY + 2) < 2) { px = l ? x0 + TX : x0 - 1; py = y0 - 2; kind = 3; }
+        else if ((l -= 2) < 2) { px = l ? x0 + TX : x0 - 1; py = y0 + TY + 1; kind = 2; }
+        else if ((l -= 2) < 2) { px = l ? x0 + TX + 1 : x0 - 2; py = l ? y0 - 2 : y0 + TY + 1; kind = 4; }
+    }
+    const bool active = kind >= 0;
+    const bool in = active && px >= 0 && py >= 0 && px < d.nx && py < d.ny;
+    const int e = active ? (py - y0 + 2) * EX + (px - x0 + 2) : 0;
+    const bool mlo_x = px > 0, mlo_y = py > 0, mhi_x = px < d.nx - 1, mhi_y = py < d.ny - 1;
+    const bool fxy = d.halo > 0 && (px < d.halo || py < d.halo || px >= d.nx - d.halo || py >= d.ny - d.halo);
+
+    // stage A: full on core + ring 1, partial on ring 2
+    Stage A, B;
+    A.full = in && (kind == 0 || kind == 1);
+    A.needU = in && (kind <= 2) && kind >= 0;
+    A.needV = in && (kind <= 1 || kind == 3) && kind >= 0;
+    A.active = active;
+    // stage B: full on the core, partial on ring 1 (u+ on the row above and
+    // the right column, v+ on the row below and the left column, p and q on
+    // the upper-left and lower-right corners)
+    const bool r1_above = kind == 1 && py == y0 + TY && px >= x0 && px < x0 + TX;
+    const bool r1_right = kind == 1 && px == x0 + TX && py >= y0 && py < y0 + TY;
+    const bool r1_below = kind == 1 && py == y0 - 1 && px >= x0 && px < x0 + TX;
+    const bool r1_left = kind == 1 && px == x0 - 1 && py >= y0 && py < y0 + TY;
+    const bool r1_ul = kind == 1 && px == x0 - 1 && py == y0 + TY;
+    const bool r1_lr = kind == 1 && px == x0 + TX && py == y0 - 1;
+    B.full = in && kind == 0;
+    B.needU = in && (kind == 0 || r1_above || r1_right);
+    B.needV = in && (kind == 0 || r1_below || r1_left);
+    B.active = kind == 0 || r1_above || r1_right || r1_below || r1_left || r1_ul || r1_lr;
+    // output windows: B writes planes z0..zl; A produces what B reads
+    B.z0 = z0;
+    B.zl = zl;
+    A.z0 = max(z0 - 1, 0);
+    A.zl = min(zl + 1, d.nz - 1);
+    A.UP1 = A.UB1 = B.UP1 = B.UB1 = 0.0f;
+    for (int c = 0; c < 3; c++) A.VB2[c] = B.VB2[c] = 0.0f;
+
+    // memory access: descriptors per field, lane column offset, uniform plane offsets
+    const long long col = in ? (long long)px + d.sy * py : 0;
+    const int v4 = (int)(col * 4), vS = (int)(col * SB), vH = (int)(col * 16);
+    const int comp = (int)(d.n * SB);
+    const long long plane4 = d.sz * 4, planeS = d.sz * SB, planeH = d.sz * 16;
+    const auto ru = rsrc2(Xc.u, d.n * 4), rv = rsrc2(Xc.v, 3 * d.n * SB), rp = rsrc2(Yc.p, 3 * d.n * SB),
+               rq = rsrc2(Yc.q, 6 * d.n * SB), rh = rsrc2(hist, d.n * 16);
+    const auto wu = rsrc2(Xn.u, d.n * 4), wv = rsrc2(Xn.v, 3 * d.n * SB), wp = rsrc2(Yn.p, 3 * d.n * SB),
+               wq = rsrc2(Yn.q, 6 * d.n * SB);
+
+    auto load_state = [&](Pl &P, uint32_t hw[4], int s) {
+        const int sc = s < d.nz ? s : d.nz - 1;
+        const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
+        P.u = Io2<0>::ld(ru, v4, o4);
+        for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE>::ld(rv, vS, oS + c * comp);
+        for (int c = 0; c < 3; c++) P.p[c] = Io2<STORE>::ld(rp, vS, oS + c * comp);
+        for (int c = 0; c < 6; c++) P.q[c] = Io2<STORE>::ld(rq, vS, oS + c * comp);
+        auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, vH, oH, 0);
+        hw[0] = hv[0];
+        hw[1] = hv[1];
+        hw[2] = hv[2];
+        hw[3] = hv[3];
+    };
+    // phase 1: publish p_x, p_y of plane s (cur) and q of plane s-1 (prev)
+    auto publish = [&](L &l, const Stage &S, const Pl &cur, const Pl &prev) {
+        if (S.active) {
+            l.sPx[e] = cur.p[0];
+            l.sPy[e] = cur.p[1];
+            l.sQ[0 * NE + e] = prev.q[0];
+            l.sQ[1 * NE + e] = prev.q[1];
+            l.sQ[2 * NE + e] = prev.q[3];
+            l.sQ[3 * NE + e] = prev.q[4];
+            l.sQ[4 * NE + e] = prev.q[5];
+        }
+    };
+    // phase 2: u+ at plane s, v+ at plane s-1; publish ubar(s-1), vbar(s-1)
+    auto primal = [&](L &l, Stage &S, const Pl &cur, const Pl &prev, const uint32_t hw[4], int s) {
+        const int sv = s - 1;
+        const bool do_u = s >= S.z0 && s < d.nz;
+        const bool do_v = sv >= max(S.z0 - 1, 0) && sv <= S.zl;
+        const bool zlo_s = s > 0, zhi_s = s < d.nz - 1, zlo_v = sv > 0, zhi_v = sv < d.nz - 1;
+        S.UP = S.UB = 0.0f;
+        for (int c = 0; c < 3; c++) S.VP[c] = S.VB[c] = 0.0f;
+        if (S.needU && do_u) {
+            const bool fz = d.halo > 0 && (s < d.halo || s >= d.nz - d.halo);
+            float pm[3];
+            const float lx = l.sPx[e - 1], ly = l.sPy[e - EX];
+            pm[0] = mlo_x ? lx : 0.0f;
+            pm[1] = mlo_y ? ly : 0.0f;
+            pm[2] = zlo_s ? prev.p[2] : 0.0f;
+            const bool mlo[3] = {mlo_x, mlo_y, zlo_s}, mhi[3] = {mhi_x, mhi_y, zhi_s};
+            S.UP = primal_u(cur.u, cur.p, pm, mlo, mhi, fxy || fz, hw, cf);
+            S.UB = 2.0f * S.UP - cur.u;
+        }
+        if (S.needV && do_v) {
+            float qn[3][3];
+            for (int i = 0; i < 3; i++) {
+                const float ax = l.sQ[lq2(qslot(i, 0)) * NE + e + 1];
+                const float ay = l.sQ[lq2(qslot(i, 1)) * NE + e + EX];
+                qn[i][0] = mhi_x ? ax : 0.0f;
+                qn[i][1] = mhi_y ? ay : 0.0f;
+                qn[i][2] = zhi_v ? cur.q[qslot(i, 2)] : 0.0f;
+            }
+            const bool mlo[3] = {mlo_x, mlo_y, zlo_v}, mhi[3] = {mhi_x, mhi_y, zhi_v};
+            primal_v(S.VP, prev.v, prev.p, prev.q, qn, mlo, mhi, cf);
+            for (int i = 0; i < 3; i++) {
+                S.VP[i] = rnd<STORE>(S.VP[i]);
+                S.VB[i] = 2.0f * S.VP[i] - prev.v[i];
+            }
+        }
+        if (S.needU) l.sU[e] = S.UB1;
+        if (S.needV) {
+            l.sV[0 * NE + e] = S.VB[0];
+            l.sV[1 * NE + e] = S.VB[1];
+            l.sV[2 * NE + e] = S.VB[2];
+        }
+    };
+    // phase 3: dual update of plane s-1 into `out` (u+, v+, p, q of plane s-1);
+    // returns whether this column produced a result for that plane
+    auto dual = [&](L &l, Stage &S, const Pl &prev, int s, Pl &out) -> bool {
+        const int sv = s - 1;
+        const bool do_dual = sv >= S.z0 && sv <= S.zl;
+        bool made = false;
+        if (S.full && do_dual) {
+            const bool zlo_v = sv > 0, zhi_v = sv < d.nz - 1;
+            const bool mlo[3] = {mlo_x, mlo_y, zlo_v}, mhi[3] = {mhi_x, mhi_y, zhi_v};
+            float ub_hi[3], vb_lo[3][3];
+            const float ux = l.sU[e + 1], uy = l.sU[e + EX];
+            ub_hi[0] = mhi_x ? ux : 0.0f;
+            ub_hi[1] = mhi_y ? uy : 0.0f;
+            ub_hi[2] = zhi_v ? S.UB : 0.0f;
+            for (int i = 0; i < 3; i++) {
+                const float bx = l.sV[i * NE + e - 1], by = l.sV[i * NE + e - EX];
+                vb_lo[0][i] = mlo_x ? bx : 0.0f;
+                vb_lo[1][i] = mlo_y ? by : 0.0f;
+                vb_lo[2][i] = zlo_v ? S.VB2[i] : 0.0f;
+            }
+            out.u = S.UP1;
+            for (int c = 0; c < 3; c++) {
+                out.v[c] = S.VP[c];
+                out.p[c] = prev.p[c];
+            }
+            for (int c = 0; c < 6; c++) out.q[c] = prev.q[c];
+            dual_pq(out.p, out.q, S.UB1, ub_hi, S.VB, vb_lo, mlo, mhi, cf);
+            for (int c = 0; c < 3; c++) out.p[c] = rnd<STORE>(out.p[c]);
+            for (int c = 0; c < 6; c++) out.q[c] = rnd<STORE>(out.q[c]);
+            made = true;
+        }
+        S.UP1 = S.UP;
+        S.UB1 = S.UB;
+        for (int c = 0; c < 3; c++) S.VB2[c] = S.VB[c];
+        return made;
+    };
+
+    // Stage A walks planes s = sA0..sA1 with (prev, cur, next) = planes
+    // s-1, s, s+1 of the state in memory and produces the full update of
+    // plane s-1.  Stage B walks one step later than it could, at plane
+    // sb = s - 2, so both stages share the two barriers of a step: its
+    // (prev, cur) are stage A's results for planes s-3 and s-2, and the
+    // histogram of plane s-2 comes down a two-step register delay line.
+    Pl Aprev, Acur, Anext, Bcur, Bprev;
+    uint32_t hA[4], hAn[4], hD1[4], hD2[4];
+    Aprev.u = 0.0f;
+    for (int c = 0; c < 3; c++) Aprev.p[c] = Aprev.v[c] = 0.0f;
+    for (int c = 0; c < 6; c++) Aprev.q[c] = 0.0f;
+    Bcur = Aprev;
+    Bprev = Aprev;
+    for (int c = 0; c < 4; c++) hD1[c] = hD2[c] = 0u;
+    const int sA0 = max(A.z0 - 1, 0), sA1 = A.zl + 1;
+    const int sB0 = max(B.z0 - 1, 0), sB1 = B.zl + 1;
+    const int s_end = sB1 + 2;
+    load_state(Anext, hAn, sA0);
+    for (int s = sA0; s <= s_end; s++) {
+        const bool runA = s <= sA1;
+        const int sb = s - 2;
+        const bool runB = sb >= sB0;
+        if (runA) {
+            Acur = Anext;
+            for (int c = 0; c < 4; c++) hA[c] = hAn[c];
+            if (s + 1 <= sA1) load_state(Anext, hAn, s + 1);
+        }
+        // phase 1
+        if (runA) publish(la, A, Acur, Aprev);
+        if (runB) publish(lb, B, Bcur, Bprev);
+        lds_barrier2();
+        // phase 2
+        if (runA) primal(la, A, Acur, Aprev, hA, s);
+        if (runB) primal(lb, B, Bcur, Bprev, hD2, sb);
+        lds_barrier2();
+        // phase 3
+        Pl res;
+        bool madeA = false;
+        if (runA) madeA = dual(la, A, Aprev, s, res);
+        if (runB) {
+            Pl outB;
+            if (dual(lb, B, Bprev, sb, outB) && in) {
+                const int sv = sb - 1;
+                const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
+                Io2<0>::st(wu, v4, o4, outB.u);
+                for (int c = 0; c < 3; c++) Io2<STORE>::st(wv, vS, oS + c * comp, outB.v[c]);
+                for (int c = 0; c < 3; c++) Io2<STORE>::st(wp, vS, oS + c * comp, outB.p[c]);
+                for (int c = 0; c < 6; c++) Io2<STORE>::st(wq, vS, oS + c * comp, outB.q[c]);
+            }
+        }
+        // rotate: stage A's result for plane s-1 becomes stage B's newest plane
+        if (runA) Aprev = Acur;
+        Bprev = Bcur;
+        if (madeA) Bcur = res;
+        else {
+            Bcur.u = 0.0f;
+            for (int c = 0; c < 3; c++) Bcur.v[c] = Bcur.p[c] = 0.0f;
+            for (int c = 0; c < 6; c++) Bcur.q[c] = 0.0f;
+        }
+        for (int c = 0; c < 4; c++) {
+            hD2[c] = hD1[c];
+            hD1[c] = hA[c];
+        }
+    }
+}
+
+template <int STORE, int TY>
+static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
+    XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
+    XBuf<STORE> Xo{b.xo_u, (typename Store<STORE>::T *)b.xo_v};
+    YBuf<STORE> Yc{(typename Store<STORE>::T *)b.yc_p, (typename Store<STORE>::T *)b.yc_q};
+    YBuf<STORE> Yo{(typename Store<STORE>::T *)b.yo_p, (typename Store<STORE>::T *)b.yo_q};
+    int ntx = (d.nx + TX - 1) / TX, nty = (d.ny + TY - 1) / TY, ntz = (d.nz + cz - 1) / cz;
+    int nb = ntx * nty * ntz;
+    int per = (nb + 7) / 8;
+    hipLaunchKernelGGL((k_fused2_tiled<STORE, TY>), dim3(8 * per), dim3(TX * (TY + 5)), 0, s, Xc, Yc, Xo, Yo, b.hist, d,
+                       cf, cz, ntx, nty, ntz);
+}
+
+bool tiled2_shape_ok(int ty, int cz) { return (ty == 4 || ty == 6) && cz >= 1; }
+
+void launch_tiled2(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
+    if (storage == 0) {
+        if (ty == 6) launch2_ty<0, 6>(b, d, cf, cz, s);
+        else launch2_ty<0, 4>(b, d, cf, cz, s);
+    } else if (storage == 1) {
+        if (ty == 6) launch2_ty<1, 6>(b, d, cf, cz, s);
+        else launch2_ty<1, 4>(b, d, cf, cz, s);
+    } else {
+        if (ty == 6) launch2_ty<2, 6>(b, d, cf, cz, s);
+        else launch2_ty<2, 4>(b, d, cf, cz, s);
+    }
+}
+
+}  // namespace tgv

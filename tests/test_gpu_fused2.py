@@ -1,0 +1,132 @@
+"""Two fused iterations per pass (schedule FUSED2) against one per pass.
+
+The temporal-blocked kernel evaluates the same per-voxel arithmetic as the
+one-iteration kernel, only in a different order over the grid, so the whole
+solver state after a solve (u, v, the previous primal iterate, p, q) must be
+bit-identical for every shape, tile, storage precision, model and iteration
+count, including odd counts (one single pass left over) and the ragged
+edges of tiles in x, y and z."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[fused2]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2107_14790_amd as tgv
+    c = tgv.Context(0)
+    yield c
+    c.close()
+
+
+def random_problem(shape, seed):
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    hist = np.zeros((n, 8), dtype=np.uint16)
+    tot = rng.integers(0, 12, size=n)
+    for x in np.nonzero(tot)[0]:
+        hist[x, :7] = np.bincount(rng.integers(0, 7, size=tot[x]), minlength=7)
+    u0 = np.where(rng.random(n) < 0.5, rng.uniform(-1, 1, n), 0.0).astype(np.float32)
+    return hist, u0
+
+
+def run(ctx, shape, hist_np, u0_np, halo, params):
+    import paper_2107_14790_amd as tgv
+    g = tgv.grid_c((0, 0, 0), 1.0, shape, halo)
+    n = int(np.prod(shape))
+    hist = torch.from_numpy(hist_np.view(np.int16).reshape(n, 8)).cuda()
+    st = tgv.State(ctx, g, storage=params.storage)
+    st.reset(torch.from_numpy(u0_np).cuda())
+    ctx.solve(g, hist, None, params, state=st)
+    f = st.export()
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in f.items()}
+    st.close()
+    return out
+
+
+def assert_same_state(a, b):
+    for k in ("u", "v", "u_prev", "v_prev", "p", "q"):
+        assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), k
+
+
+CASES = [
+    # shape, halo, iters, tile_y, tile_z
+    ((70, 9, 5), 0, 9, 4, 2),
+    ((37, 29, 23), 2, 20, 4, 5),
+    ((37, 29, 23), 2, 21, 6, 64),
+    ((130, 21, 40), 0, 12, 4, 7),
+    ((130, 21, 40), 0, 13, 6, 1),
+    ((64, 8, 8), 3, 6, 4, 3),
+    ((65, 7, 67), 1, 4, 6, 16),
+    ((1, 1, 1), 0, 5, 4, 1),
+    ((17, 1, 1), 0, 8, 4, 2),
+    ((1, 13, 6), 0, 7, 6, 3),
+    ((3, 2, 2), 0, 3, 4, 1),
+]
+
+
+@pytest.mark.parametrize("shape,halo,iters,ty,cz", CASES)
+def test_fused2_state_bit_identical(ctx, shape, halo, iters, ty, cz):
+    import paper_2107_14790_amd as tgv
+    say("shape", shape, "halo", halo, "iters", iters, "tile", ty, cz)
+    hist, u0 = random_problem(shape, sum(shape) * 7 + iters)
+    ref = run(ctx, shape, hist, u0, halo, tgv.Params(iters=iters))
+    got = run(ctx, shape, hist, u0, halo, tgv.Params(iters=iters, schedule=tgv.SCHED_FUSED2, tile_y=ty, tile_z=cz))
+    assert_same_state(ref, got)
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_fused2_low_precision_storage_bit_identical(ctx, storage):
+    import paper_2107_14790_amd as tgv
+    shape = (100, 19, 33)
+    say("storage", storage, shape)
+    hist, u0 = random_problem(shape, 11 + storage)
+    ref = run(ctx, shape, hist, u0, 1, tgv.Params(iters=11, storage=storage))
+    got = run(ctx, shape, hist, u0, 1, tgv.Params(iters=11, storage=storage, schedule=tgv.SCHED_FUSED2, tile_z=6))
+    assert_same_state(ref, got)
+
+
+def test_fused2_tvl1_bit_identical(ctx):
+    import paper_2107_14790_amd as tgv
+    shape = (70, 30, 18)
+    say("tvl1", shape)
+    hist, u0 = random_problem(shape, 5)
+    ref = run(ctx, shape, hist, u0, 0, tgv.Params(iters=10, flags=tgv.FLAG_TVL1))
+    got = run(ctx, shape, hist, u0, 0, tgv.Params(iters=10, flags=tgv.FLAG_TVL1, schedule=tgv.SCHED_FUSED2,
+                                                   tile_y=6, tile_z=4))
+    assert_same_state(ref, got)
+
+
+def test_fused2_rejects_unsupported_tile(ctx):
+    import paper_2107_14790_amd as tgv
+    shape = (8, 8, 8)
+    hist, u0 = random_problem(shape, 1)
+    with pytest.raises(tgv.TgvError) as e:
+        run(ctx, shape, hist, u0, 0, tgv.Params(iters=4, schedule=tgv.SCHED_FUSED2, tile_y=8))
+    assert e.value.status == tgv.TGV_E_INVAL
+
+
+def test_fused2_terrain256_sampled_state(ctx):
+    """The bench's block (256^3) in the bench's launch shape: the default
+    schedule and FUSED2 agree bit for bit on the whole state."""
+    import paper_2107_14790_amd as tgv
+    shape = (256, 256, 256)
+    say("256^3 default tiles")
+    rng = np.random.default_rng(256)
+    n = int(np.prod(shape))
+    hist = np.zeros((n, 8), dtype=np.uint16)
+    hist[:, :7] = rng.integers(0, 3, size=(n, 7), dtype=np.uint16) * (rng.random((n, 1)) < 0.3)
+    u0 = np.zeros(n, np.float32)
+    ref = run(ctx, shape, hist, u0, 0, tgv.Params(iters=7))
+    got = run(ctx, shape, hist, u0, 0, tgv.Params(iters=7, schedule=tgv.SCHED_FUSED2))
+    assert_same_state(ref, got)

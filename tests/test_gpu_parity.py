@@ -365,8 +365,12 @@ def test_crossings_of_solved_sphere(ctx):
     pts = ctx.extract_crossings(g, torch.from_numpy(u32).cuda()).cpu().numpy()
     ref = oracle.crossings(u32, (32, 32, 32), sc.grid.origin, sc.grid.h)
     assert np.array_equal(pts.view(np.uint32), ref.view(np.uint32))
-    r = np.linalg.norm(pts[:, :3], axis=1)
-    assert len(pts) > 1000 and np.median(np.abs(r - 1.0)) < 0.05  # the surface is the unit sphere
+    # the ring cameras see the sphere near their plane; above and below it
+    # the data term is empty and u hovers around 0, so only that band is
+    # checked against the unit sphere
+    band = np.abs(pts[:, 2]) < 0.5
+    r = np.linalg.norm(pts[band, :3], axis=1)
+    assert band.sum() > 500 and np.median(np.abs(r - 1.0)) < 0.03 and np.percentile(np.abs(r - 1.0), 90) < 0.06
 
 
 # ---------------------------------------------------------------------------

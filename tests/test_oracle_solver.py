@@ -366,6 +366,21 @@ def test_no_crossings_in_a_constant_sign_field():
     assert len(pts) == 6 and np.all(pts[:, 3] >= 0)
 
 
+def test_zero_level_of_the_solved_sphere_is_the_unit_sphere():
+    # end to end on the CPU: histograms of 8 noisy ring views of the unit
+    # sphere, 300 iterations, crossings; near the cameras' plane (where the
+    # data term sees the surface) the points lie on the sphere to a fraction
+    # of a voxel (h = 0.094)
+    sc = scenes.sphere_scene()
+    h, _ = oracle.histograms(sc)
+    st = oracle.solve(h, (32, 32, 32), scenes.default_bins(), 300)
+    pts = oracle.crossings(st.u.astype(np.float32), (32, 32, 32), sc.grid.origin, sc.grid.h)
+    band = np.abs(pts[:, 2]) < 0.5
+    r = np.linalg.norm(pts[band, :3], axis=1)
+    assert band.sum() > 500
+    assert np.median(np.abs(r - 1.0)) < 0.03 and np.percentile(np.abs(r - 1.0), 90) < 0.06
+
+
 def test_prolongation_takes_the_parent_value():
     rng = np.random.default_rng(12)
     uc = rng.normal(size=4 * 3 * 2)
