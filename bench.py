@@ -230,9 +230,9 @@ def bench_block(args):
         bpv = fused_bytes_per_voxel(storage)
         achieved = bpv * nvox / (k_ms * 1e-3) / 1e9
         if args.schedule == "fused2":
-            tile = f"{params.tile_y or 4}x{params.tile_z or 64}"
+            tile = f"{params.tile_y or 6}x{params.tile_z or 64}"
         else:
-            tile = f"{params.tile_y or 4}x{params.tile_z or 32}"
+            tile = f"{params.tile_y or (8 if storage == 0 else 4)}x{params.tile_z or 32}"
         traffic = measured_traffic(storage, tile, args.schedule) if n == 256 else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, tile=tile,

@@ -575,7 +575,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
                 st->xc ^= 1;
             }
         } else {
-            int ty = params->tile_y ? params->tile_y : DEFAULT_TILE_Y;
+            int ty = params->tile_y ? params->tile_y : default_tile_y(st->storage);
             int cz = params->tile_z ? params->tile_z : DEFAULT_TILE_Z;
             int it = 0;
             if (params->schedule == TGV_SCHED_FUSED2 && tiled_fits(d)) {
@@ -589,7 +589,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
                     st->xc ^= 1;
                     st->yc ^= 1;
                 }
-                ty = DEFAULT_TILE_Y;
+                ty = default_tile_y(st->storage);
             }
             for (; it + 1 < N; it++) {
                 SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
@@ -647,7 +647,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
     hipStream_t s = S(stream);
     Coef cf = make_coef(*params, *bins);
     const int N = params->iters;
-    const int ty = params->tile_y ? params->tile_y : DEFAULT_TILE_Y;
+    const int ty = params->tile_y ? params->tile_y : DEFAULT_BATCH_TILE_Y;
     if (!tiled_shape_ok(ty, 1)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: tile_y %d", ty);
     if (n == 0 || N == 0) {
         if (stats_host)

@@ -69,10 +69,14 @@ struct EnergyOut {
 int64_t storage_bytes(int storage);
 
 void launch_ref(int kind, int storage, const SolveBufs &b, const Dims &d, const Coef &cf, hipStream_t s);
-constexpr int DEFAULT_TILE_Y = 4;
+// default tiles (measured on a 256^3 block): 64 x 8 x 32 for float32
+// storage, 64 x 4 x 32 for 16-bit storage; FUSED2 64 x 6 x 64; the batched
+// solve defaults to 64 x 4
 constexpr int DEFAULT_TILE_Z = 32;
-constexpr int DEFAULT_TILE2_Y = 4;
+constexpr int DEFAULT_BATCH_TILE_Y = 4;
+constexpr int DEFAULT_TILE2_Y = 6;
 constexpr int DEFAULT_TILE2_Z = 64;
+inline int default_tile_y(int storage) { return storage == 0 ? 8 : 4; }
 bool tiled_shape_ok(int ty, int cz);
 void launch_tiled(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);
 bool tiled_fits(const Dims &d);

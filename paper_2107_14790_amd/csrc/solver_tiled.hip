@@ -329,8 +329,14 @@ __device__ __forceinline__ void run_tile(TileLds<TY> &lds, const XBuf<STORE> &Xc
     }
 }
 
+// Occupancy target of the one-block kernel per configuration (measured):
+// float32 storage with 64 x 8 tiles fits 80 VGPRs without spilling, which
+// gives 6 waves per SIMD and two workgroups of 11 waves per CU; the other
+// configurations are fastest with the default register budget.
+constexpr int tiled_waves(int store, int ty) { return (store == 0 && ty == 8) ? 6 : TILED_WAVES_PER_EU; }
+
 template <int STORE, int TY>
-__global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc,
+__global__ void __launch_bounds__(TX *(TY + 3), tiled_waves(STORE, TY)) k_fused_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc,
                                                                                   XBuf<STORE> Xn, YBuf<STORE> Yn,
                                                                                   const uint16_t *__restrict__ hist,
                                                                                   Dims d, Coef cf, int CZ, int ntx,
