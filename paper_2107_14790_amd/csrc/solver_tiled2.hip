@@ -66,6 +66,23 @@ struct Io2<2> {
     }
 };
 
+// Fields a lane loads (bit mask).  A skipped field gets a lane offset past
+// the end of its buffer, so the load returns 0 without a memory request
+// (raw buffer range check).
+enum : int {
+    LD2_U = 1 << 0,
+    LD2_V = 1 << 1,
+    LD2_PX = 1 << 2,
+    LD2_PY = 1 << 3,
+    LD2_PZ = 1 << 4,
+    LD2_Q0 = 1 << 5,  // q slot k: LD2_Q0 << k
+    LD2_H = 1 << 11,
+    LD2_P = LD2_PX | LD2_PY | LD2_PZ,
+    LD2_Q = 63 * LD2_Q0,
+    LD2_ALL = LD2_U | LD2_V | LD2_P | LD2_Q | LD2_H,
+};
+constexpr int LD2_SKIP = (int)0x80000000u;  // >= every buffer's size (below 2^31 for tiled blocks)
+
 // the state of one column at one plane
 struct Pl {
     float u, v[3], p[3], q[6];
@@ -118,24 +135,41 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     int px = -3, py = -3;
     // kind: 0 core, 1 ring-1, 2 ring-2 needing u+, 3 ring-2 needing v+, 4 ring-2 corner, -1 none
     int kind = -1;
-    if (w < TY) { px = x0 + lane; py = y0 + w; kind = 0; }
-    else if (w == TY) { px = x0 + lane; py = y0 - 1; kind = 1; }
-    else if (w == TY + 1) { px = x0 + lane; py = y0 + TY; kind = 1; }
-    else if (w == TY + 2) { px = x0 + lane; py = y0 - 2; kind = 3; }
-    else if (w == TY + 3) { px = x0 + lane; py = y0 + TY + 1; kind = 2; }
+    // Load masks (stage B loads nothing): the tile and the first ring read
+    // every field; the second ring reads what stage A's partial updates
+    // there use: v, p and q where v+ is formed (bottom row, left column);
+    // u, p, the histogram and the q components the first ring's v+ takes
+    // from it where u+ is formed (q_iy on the top row, q_ix on the right
+    // column); p_x and q_iy (upper-left corner) or p_y and q_ix (lower-right).
+    constexpr int Q_IX = LD2_Q0 << 0 | LD2_Q0 << 3 | LD2_Q0 << 4;  // xx, xy, xz
+    constexpr int Q_IY = LD2_Q0 << 1 | LD2_Q0 << 3 | LD2_Q0 << 5;  // yy, xy, yz
+    constexpr int M_V = LD2_V | LD2_P | LD2_Q, M_TOP = LD2_U | LD2_P | LD2_H | Q_IY,
+                  M_RIGHT = LD2_U | LD2_P | LD2_H | Q_IX;
+    int lm = 0;
+    if (w < TY) { px = x0 + lane; py = y0 + w; kind = 0; lm = LD2_ALL; }
+    else if (w == TY) { px = x0 + lane; py = y0 - 1; kind = 1; lm = LD2_ALL; }
+    else if (w == TY + 1) { px = x0 + lane; py = y0 + TY; kind = 1; lm = LD2_ALL; }
+    else if (w == TY + 2) { px = x0 + lane; py = y0 - 2; kind = 3; lm = M_V; }
+    else if (w == TY + 3) { px = x0 + lane; py = y0 + TY + 1; kind = 2; lm = M_TOP; }
     else {
         int l = lane;
-        if (l < TY) { px = x0 - 1; py = y0 + l; kind = 1; }
-        else if ((l -= TY) < TY) { px = x0 + TX; py = y0 + l; kind = 1; }
-        else if ((l -= TY) < 4) { px = (l & 1) ? x0 + TX : x0 - 1; py = (l & 2) ? y0 + TY : y0 - 1; kind = 1; }
-        else if ((l -= 4) < TY + 2) { px = x0 - 2; py = y0 - 1 + l; kind = 3; }
-        else if ((l -= TY + 2) < TY + 2) { px = x0 + TX + 1; py = y0 - 1 + l; kind = 2; }
-        else if ((l -= TY + 2) < 2) { px = l ? x0 + TX : x0 - 1; py = y0 - 2; kind = 3; }
-        else if ((l -= 2) < 2) { px = l ? x0 + TX : x0 - 1; py = y0 + TY + 1; kind = 2; }
-        else if ((l -= 2) < 2) { px = l ? x0 + TX + 1 : x0 - 2; py = l ? y0 - 2 : y0 + TY + 1; kind = 4; }
+        if (l < TY) { px = x0 - 1; py = y0 + l; kind = 1; lm = LD2_ALL; }
+        else if ((l -= TY) < TY) { px = x0 + TX; py = y0 + l; kind = 1; lm = LD2_ALL; }
+        else if ((l -= TY) < 4) {
+            px = (l & 1) ? x0 + TX : x0 - 1; py = (l & 2) ? y0 + TY : y0 - 1; kind = 1; lm = LD2_ALL;
+        }
+        else if ((l -= 4) < TY + 2) { px = x0 - 2; py = y0 - 1 + l; kind = 3; lm = M_V; }
+        else if ((l -= TY + 2) < TY + 2) { px = x0 + TX + 1; py = y0 - 1 + l; kind = 2; lm = M_RIGHT; }
+        else if ((l -= TY + 2) < 2) { px = l ? x0 + TX : x0 - 1; py = y0 - 2; kind = 3; lm = M_V; }
+        else if ((l -= 2) < 2) { px = l ? x0 + TX : x0 - 1; py = y0 + TY + 1; kind = 2; lm = M_TOP; }
+        else if ((l -= 2) < 2) {
+            px = l ? x0 + TX + 1 : x0 - 2; py = l ? y0 - 2 : y0 + TY + 1; kind = 4;
+            lm = l ? (LD2_PY | Q_IX) : (LD2_PX | Q_IY);
+        }
     }
     const bool active = kind >= 0;
     const bool in = active && px >= 0 && py >= 0 && px < d.nx && py < d.ny;
+    const int lmask = in ? lm : 0;
     const int e = active ? (py - y0 + 2) * EX + (px - x0 + 2) : 0;
     const bool mlo_x = px > 0, mlo_y = py > 0, mhi_x = px < d.nx - 1, mhi_y = py < d.ny - 1;
     const bool fxy = d.halo > 0 && (px < d.halo || py < d.halo || px >= d.nx - d.halo || py >= d.ny - d.halo);
@@ -180,11 +214,13 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     auto load_state = [&](Pl &P, uint32_t hw[4], int s) {
         const int sc = s < d.nz ? s : d.nz - 1;
         const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
-        P.u = Io2<0>::ld(ru, v4, o4);
-        for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE>::ld(rv, vS, oS + c * comp);
-        for (int c = 0; c < 3; c++) P.p[c] = Io2<STORE>::ld(rp, vS, oS + c * comp);
-        for (int c = 0; c < 6; c++) P.q[c] = Io2<STORE>::ld(rq, vS, oS + c * comp);
-        auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, vH, oH, 0);
+        const int m = lmask;
+        P.u = Io2<0>::ld(ru, (m & LD2_U) ? v4 : LD2_SKIP, o4);
+        const int ov = (m & LD2_V) ? vS : LD2_SKIP;
+        for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE>::ld(rv, ov, oS + c * comp);
+        for (int c = 0; c < 3; c++) P.p[c] = Io2<STORE>::ld(rp, (m & (LD2_PX << c)) ? vS : LD2_SKIP, oS + c * comp);
+        for (int c = 0; c < 6; c++) P.q[c] = Io2<STORE>::ld(rq, (m & (LD2_Q0 << c)) ? vS : LD2_SKIP, oS + c * comp);
+        auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, (m & LD2_H) ? vH : LD2_SKIP, oH, 0);
         hw[0] = hv[0];
         hw[1] = hv[1];
         hw[2] = hv[2];
