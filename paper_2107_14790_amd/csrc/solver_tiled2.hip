@@ -20,6 +20,11 @@
 #ifndef TILED2_WAVES_PER_EU
 #define TILED2_WAVES_PER_EU 3
 #endif
+// cache policy of the result stores: non-temporal (bit 2 on gfx950), as in
+// the one-iteration kernel
+#ifndef TILED2_ST_CP
+#define TILED2_ST_CP 2
+#endif
 
 namespace tgv {
 
@@ -42,7 +47,7 @@ struct Io2<0> {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, TILED2_ST_CP);
     }
 };
 template <>
@@ -51,7 +56,7 @@ struct Io2<1> {
         return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, TILED2_ST_CP);
     }
 };
 template <>
@@ -62,7 +67,7 @@ struct Io2<2> {
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
         bf16_t t;
         Store<2>::st(&t, v);
-        __builtin_amdgcn_raw_buffer_store_b16(t.bits, r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(t.bits, r, voff, soff, TILED2_ST_CP);
     }
 };
 
