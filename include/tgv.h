@@ -98,9 +98,10 @@ enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1, TGV_SCHED_FUSED_REF = 2, TGV_SC
 /* Solver parameters (Eq. 2, Sec. 3.2).  tau, sigma: primal and dual step
  * sizes (> 0); iters >= 0 primal-dual iterations.  tile_y, tile_z: shape of
  * the fused kernel's tiles (64 x tile_y columns, tile_z planes per
- * workgroup); 0 picks the library default: 64 x 8 x 32 for float32
- * storage, 64 x 4 x 32 for 16-bit storage, 64 x 6 x 64 for FUSED2, 64 x 4
- * for a batched solve (tile_y in {4, 8, 12}; in {4, 6} for FUSED2). */
+ * workgroup); 0 picks the library default: 64 x 8 x 32 for a float32
+ * block whose iteration moves more than 256 MiB, else 64 x 4 x 32;
+ * 64 x 6 x 64 for FUSED2; 64 x 4 for a batched solve (tile_y in {4, 8, 12};
+ * in {4, 6} for FUSED2). */
 typedef struct {
     float alpha0, alpha1, lambda;
     float tau, sigma;

@@ -575,7 +575,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
                 st->xc ^= 1;
             }
         } else {
-            int ty = params->tile_y ? params->tile_y : default_tile_y(st->storage);
+            int ty = params->tile_y ? params->tile_y : default_tile_y(st->storage, d);
             int cz = params->tile_z ? params->tile_z : DEFAULT_TILE_Z;
             int it = 0;
             if (params->schedule == TGV_SCHED_FUSED2 && tiled_fits(d)) {
@@ -589,7 +589,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
                     st->xc ^= 1;
                     st->yc ^= 1;
                 }
-                ty = default_tile_y(st->storage);
+                ty = default_tile_y(st->storage, d);
             }
             for (; it + 1 < N; it++) {
                 SolveBufs b = bufs_of(st, st->xc, st->yc, hist);

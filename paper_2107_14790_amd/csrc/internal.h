@@ -69,17 +69,34 @@ struct EnergyOut {
 int64_t storage_bytes(int storage);
 
 void launch_ref(int kind, int storage, const SolveBufs &b, const Dims &d, const Coef &cf, hipStream_t s);
-// default tiles (measured on a 256^3 block): 64 x 8 x 32 for float32
-// storage, 64 x 4 x 32 for 16-bit storage; FUSED2 64 x 6 x 64; the batched
-// solve defaults to 64 x 4
+
+bool tiled_shape_ok(int ty, int cz);
+void launch_tiled(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);
+bool tiled_fits(const Dims &d);
+// Cache policy of the fused kernels' result stores: non-temporal (buffer
+// instruction bit 2 on gfx950) when one iteration moves more than the
+// 256 MiB infinity cache holds.  Such a block's results are not read again
+// before they would be evicted, and streaming them leaves the L2 to the
+// input rows that neighbouring tiles read as their ring (256^3 block: 6 %
+// fewer HBM reads, 6 % faster); a smaller block's results are read back
+// from the infinity cache by the next iteration, which write-back stores
+// allow (city blocks of 36^3..132^3: 16 % faster than streamed).  The
+// batched kernel, which also runs small blocks, always uses write-back.
+constexpr int STORE_CP_STREAM = 2;
+inline bool stream_stores(int storage, const Dims &d) {
+    const long long per_voxel = storage == 0 ? 120 : 72;
+    return d.n * per_voxel > (256LL << 20);
+}
+
+// Default tiles (measured): 64 x 8 x 32 for a float32 block larger than the
+// infinity cache (256^3: 5 % faster than 64 x 4), else 64 x 4 x 32 (city
+// blocks: 3 % faster than 64 x 8; 16-bit storage at 256^3: 64 x 4 is
+// fastest); FUSED2 64 x 6 x 64; the batched solve defaults to 64 x 4.
 constexpr int DEFAULT_TILE_Z = 32;
 constexpr int DEFAULT_BATCH_TILE_Y = 4;
 constexpr int DEFAULT_TILE2_Y = 6;
 constexpr int DEFAULT_TILE2_Z = 64;
-inline int default_tile_y(int storage) { return storage == 0 ? 8 : 4; }
-bool tiled_shape_ok(int ty, int cz);
-void launch_tiled(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);
-bool tiled_fits(const Dims &d);
+inline int default_tile_y(int storage, const Dims &d) { return (storage == 0 && stream_stores(storage, d)) ? 8 : 4; }
 // two fused iterations per launch (temporal blocking), tiles 64 x ty (ty in {4, 6})
 bool tiled2_shape_ok(int ty, int cz);
 void launch_tiled2(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);

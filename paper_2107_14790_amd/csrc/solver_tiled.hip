@@ -22,14 +22,7 @@
 #ifndef TILED_WAVES_PER_EU
 #define TILED_WAVES_PER_EU 4
 #endif
-// Cache policy of the result stores (buffer instruction bits on gfx950:
-// 1 = sc0, 2 = nt, 16 = sc1).  The results are not read again in this
-// pass, so they are stored non-temporal: the L2 then keeps the input rows
-// that neighbouring tiles read as their ring longer (measured on a 256^3
-// block: 6 % fewer HBM reads, 6 % faster).
-#ifndef TILED_ST_CP
-#define TILED_ST_CP 2
-#endif
+
 
 namespace tgv {
 
@@ -100,7 +93,7 @@ struct Plane {
 // q components the in-plane neighbours read: xx, yy, xy, xz, yz (q slots 0, 1, 3, 4, 5)
 __device__ __forceinline__ int lq_of_slot(int slot) { return slot == 0 ? 0 : (slot == 1 ? 1 : slot - 1); }
 
-template <int STORE, int TY>
+template <int STORE, int TY, int SCP>
 struct Tile {
     static constexpr int EX = TX + 2, EY = TY + 2, NE = EX * EY;
     static constexpr int SB = STORE == 0 ? 4 : 2;  // bytes per stored v/p/q element
@@ -222,13 +215,13 @@ struct Tile {
             dual_pq(p, q, UB1, ub_hi, VB, vb_lo, mlo, mhi, *cf);
             if (in) {
                 const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
-                Io<0>::st<TILED_ST_CP>(wu, v4, o4, UP1);
+                Io<0>::st<SCP>(wu, v4, o4, UP1);
 #pragma unroll
-                for (int c = 0; c < 3; c++) Io<STORE>::template st<TILED_ST_CP>(wv, vS, oS + c * comp, VP[c]);
+                for (int c = 0; c < 3; c++) Io<STORE>::template st<SCP>(wv, vS, oS + c * comp, VP[c]);
 #pragma unroll
-                for (int c = 0; c < 3; c++) Io<STORE>::template st<TILED_ST_CP>(wp, vS, oS + c * comp, p[c]);
+                for (int c = 0; c < 3; c++) Io<STORE>::template st<SCP>(wp, vS, oS + c * comp, p[c]);
 #pragma unroll
-                for (int c = 0; c < 6; c++) Io<STORE>::template st<TILED_ST_CP>(wq, vS, oS + c * comp, q[c]);
+                for (int c = 0; c < 6; c++) Io<STORE>::template st<SCP>(wq, vS, oS + c * comp, q[c]);
             }
         }
         UP1 = UP;
@@ -254,11 +247,11 @@ struct TileLds {
 // One fused iteration on tile (tix, tiy, tiz) of a block: X/Y current
 // buffers in, Xn/Yn out.  Every thread of the workgroup must call this
 // (it contains workgroup barriers).
-template <int STORE, int TY>
+template <int STORE, int TY, int SCP>
 __device__ __forceinline__ void run_tile(TileLds<TY> &lds, const XBuf<STORE> &Xc, const YBuf<STORE> &Yc,
                                          const XBuf<STORE> &Xn, const YBuf<STORE> &Yn, const uint16_t *hist,
                                          const Dims &d, const Coef &cf, int CZ, int tix, int tiy, int tiz) {
-    using T = Tile<STORE, TY>;
+    using T = Tile<STORE, TY, SCP>;
     constexpr int EX = T::EX;
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * CZ;
 
@@ -351,7 +344,7 @@ __device__ __forceinline__ void run_tile(TileLds<TY> &lds, const XBuf<STORE> &Xc
 // configurations are fastest with the default register budget.
 constexpr int tiled_waves(int store, int ty) { return (store == 0 && ty == 8) ? 6 : TILED_WAVES_PER_EU; }
 
-template <int STORE, int TY>
+template <int STORE, int TY, int SCP>
 __global__ void __launch_bounds__(TX *(TY + 3), tiled_waves(STORE, TY)) k_fused_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc,
                                                                                   XBuf<STORE> Xn, YBuf<STORE> Yn,
                                                                                   const uint16_t *__restrict__ hist,
@@ -364,7 +357,7 @@ __global__ void __launch_bounds__(TX *(TY + 3), tiled_waves(STORE, TY)) k_fused_
     const int per = (nb + 7) / 8;
     const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (L >= nb) return;
-    run_tile<STORE, TY>(lds, Xc, Yc, Xn, Yn, hist, d, cf, CZ, L % ntx, (L / ntx) % nty, L / (ntx * nty));
+    run_tile<STORE, TY, SCP>(lds, Xc, Yc, Xn, Yn, hist, d, cf, CZ, L % ntx, (L / ntx) % nty, L / (ntx * nty));
 }
 
 // ---------------------------------------------------------------------------
@@ -399,7 +392,7 @@ __global__ void __launch_bounds__(TX *(TY + 3), TILED_WAVES_PER_EU) k_fused_batc
             XBuf<STORE> Xn{bb.u[xc ^ 1], (typename Store<STORE>::T *)bb.v[xc ^ 1]};
             YBuf<STORE> Yc{(typename Store<STORE>::T *)bb.p[yc], (typename Store<STORE>::T *)bb.q[yc]};
             YBuf<STORE> Yn{(typename Store<STORE>::T *)bb.p[yc ^ 1], (typename Store<STORE>::T *)bb.q[yc ^ 1]};
-            run_tile<STORE, TY>(lds, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz, tr.y & 0xffff, tr.y >> 16, tr.z);
+            run_tile<STORE, TY, 0>(lds, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz, tr.y & 0xffff, tr.y >> 16, tr.z);
             lds_barrier();  // the tile's LDS reads are done before the next tile writes
         }
     }
@@ -409,7 +402,7 @@ __global__ void k_reset_counters(int *counters) {
     if (threadIdx.x < 8) counters[threadIdx.x] = 0;
 }
 
-template <int STORE, int TY>
+template <int STORE, int TY, int SCP>
 static void launch_tiled_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
     XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
     XBuf<STORE> Xo{b.xo_u, (typename Store<STORE>::T *)b.xo_v};
@@ -418,15 +411,15 @@ static void launch_tiled_ty(const SolveBufs &b, const Dims &d, const Coef &cf, i
     int ntx = (d.nx + TX - 1) / TX, nty = (d.ny + TY - 1) / TY, ntz = (d.nz + cz - 1) / cz;
     int nb = ntx * nty * ntz;
     int per = (nb + 7) / 8;
-    hipLaunchKernelGGL((k_fused_tiled<STORE, TY>), dim3(8 * per), dim3(TX * (TY + 3)), 0, s, Xc, Yc, Xo, Yo, b.hist, d, cf,
-                       cz, ntx, nty, ntz);
+    hipLaunchKernelGGL((k_fused_tiled<STORE, TY, SCP>), dim3(8 * per), dim3(TX * (TY + 3)), 0, s, Xc, Yc, Xo, Yo, b.hist, d,
+                       cf, cz, ntx, nty, ntz);
 }
 
-template <int STORE>
+template <int STORE, int SCP>
 static void launch_tiled_t(const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
-    if (ty == 4) launch_tiled_ty<STORE, 4>(b, d, cf, cz, s);
-    else if (ty == 12) launch_tiled_ty<STORE, 12>(b, d, cf, cz, s);
-    else launch_tiled_ty<STORE, 8>(b, d, cf, cz, s);
+    if (ty == 4) launch_tiled_ty<STORE, 4, SCP>(b, d, cf, cz, s);
+    else if (ty == 12) launch_tiled_ty<STORE, 12, SCP>(b, d, cf, cz, s);
+    else launch_tiled_ty<STORE, 8, SCP>(b, d, cf, cz, s);
 }
 
 bool tiled_shape_ok(int ty, int cz) { return (ty == 4 || ty == 8 || ty == 12) && cz >= 1; }
@@ -463,9 +456,15 @@ void launch_tiled(int storage, const SolveBufs &b, const Dims &d, const Coef &cf
         launch_ref(KIND_FUSED, storage, b, d, cf, s);
         return;
     }
-    if (storage == 0) launch_tiled_t<0>(b, d, cf, ty, cz, s);
-    else if (storage == 1) launch_tiled_t<1>(b, d, cf, ty, cz, s);
-    else launch_tiled_t<2>(b, d, cf, ty, cz, s);
+    if (stream_stores(storage, d)) {
+        if (storage == 0) launch_tiled_t<0, STORE_CP_STREAM>(b, d, cf, ty, cz, s);
+        else if (storage == 1) launch_tiled_t<1, STORE_CP_STREAM>(b, d, cf, ty, cz, s);
+        else launch_tiled_t<2, STORE_CP_STREAM>(b, d, cf, ty, cz, s);
+    } else {
+        if (storage == 0) launch_tiled_t<0, 0>(b, d, cf, ty, cz, s);
+        else if (storage == 1) launch_tiled_t<1, 0>(b, d, cf, ty, cz, s);
+        else launch_tiled_t<2, 0>(b, d, cf, ty, cz, s);
+    }
 }
 
 }  // namespace tgv

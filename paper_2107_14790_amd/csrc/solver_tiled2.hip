@@ -20,11 +20,7 @@
 #ifndef TILED2_WAVES_PER_EU
 #define TILED2_WAVES_PER_EU 3
 #endif
-// cache policy of the result stores: non-temporal (bit 2 on gfx950), as in
-// the one-iteration kernel
-#ifndef TILED2_ST_CP
-#define TILED2_ST_CP 2
-#endif
+
 
 namespace tgv {
 
@@ -46,8 +42,9 @@ struct Io2<0> {
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
     }
+    template <int CP>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, TILED2_ST_CP);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, CP);
     }
 };
 template <>
@@ -55,8 +52,9 @@ struct Io2<1> {
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
     }
+    template <int CP>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, TILED2_ST_CP);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, CP);
     }
 };
 template <>
@@ -64,10 +62,11 @@ struct Io2<2> {
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
     }
+    template <int CP>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
         bf16_t t;
         Store<2>::st(&t, v);
-        __builtin_amdgcn_raw_buffer_store_b16(t.bits, r, voff, soff, TILED2_ST_CP);
+        __builtin_amdgcn_raw_buffer_store_b16(t.bits, r, voff, soff, CP);
     }
 };
 
@@ -116,7 +115,7 @@ struct Stage {
 
 }  // namespace
 
-template <int STORE, int TY>
+template <int STORE, int TY, int SCP>
 __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     k_fused2_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn, YBuf<STORE> Yn, const uint16_t *__restrict__ hist,
                    Dims d, Coef cf, int CZ, int ntx, int nty, int ntz) {
@@ -366,10 +365,10 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
             if (dual(lb, B, Bprev, sb, outB) && in) {
                 const int sv = sb - 1;
                 const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
-                Io2<0>::st(wu, v4, o4, outB.u);
-                for (int c = 0; c < 3; c++) Io2<STORE>::st(wv, vS, oS + c * comp, outB.v[c]);
-                for (int c = 0; c < 3; c++) Io2<STORE>::st(wp, vS, oS + c * comp, outB.p[c]);
-                for (int c = 0; c < 6; c++) Io2<STORE>::st(wq, vS, oS + c * comp, outB.q[c]);
+                Io2<0>::st<SCP>(wu, v4, o4, outB.u);
+                for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wv, vS, oS + c * comp, outB.v[c]);
+                for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wp, vS, oS + c * comp, outB.p[c]);
+                for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, oS + c * comp, outB.q[c]);
             }
         }
         // rotate: stage A's result for plane s-1 becomes stage B's newest plane
@@ -388,7 +387,7 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     }
 }
 
-template <int STORE, int TY>
+template <int STORE, int TY, int SCP>
 static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
     XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
     XBuf<STORE> Xo{b.xo_u, (typename Store<STORE>::T *)b.xo_v};
@@ -397,22 +396,27 @@ static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz
     int ntx = (d.nx + TX - 1) / TX, nty = (d.ny + TY - 1) / TY, ntz = (d.nz + cz - 1) / cz;
     int nb = ntx * nty * ntz;
     int per = (nb + 7) / 8;
-    hipLaunchKernelGGL((k_fused2_tiled<STORE, TY>), dim3(8 * per), dim3(TX * (TY + 5)), 0, s, Xc, Yc, Xo, Yo, b.hist, d,
-                       cf, cz, ntx, nty, ntz);
+    hipLaunchKernelGGL((k_fused2_tiled<STORE, TY, SCP>), dim3(8 * per), dim3(TX * (TY + 5)), 0, s, Xc, Yc, Xo, Yo, b.hist,
+                       d, cf, cz, ntx, nty, ntz);
+}
+
+template <int STORE, int SCP>
+static void launch2_t(const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
+    if (ty == 6) launch2_ty<STORE, 6, SCP>(b, d, cf, cz, s);
+    else launch2_ty<STORE, 4, SCP>(b, d, cf, cz, s);
 }
 
 bool tiled2_shape_ok(int ty, int cz) { return (ty == 4 || ty == 6) && cz >= 1; }
 
 void launch_tiled2(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
-    if (storage == 0) {
-        if (ty == 6) launch2_ty<0, 6>(b, d, cf, cz, s);
-        else launch2_ty<0, 4>(b, d, cf, cz, s);
-    } else if (storage == 1) {
-        if (ty == 6) launch2_ty<1, 6>(b, d, cf, cz, s);
-        else launch2_ty<1, 4>(b, d, cf, cz, s);
+    if (stream_stores(storage, d)) {
+        if (storage == 0) launch2_t<0, STORE_CP_STREAM>(b, d, cf, ty, cz, s);
+        else if (storage == 1) launch2_t<1, STORE_CP_STREAM>(b, d, cf, ty, cz, s);
+        else launch2_t<2, STORE_CP_STREAM>(b, d, cf, ty, cz, s);
     } else {
-        if (ty == 6) launch2_ty<2, 6>(b, d, cf, cz, s);
-        else launch2_ty<2, 4>(b, d, cf, cz, s);
+        if (storage == 0) launch2_t<0, 0>(b, d, cf, ty, cz, s);
+        else if (storage == 1) launch2_t<1, 0>(b, d, cf, ty, cz, s);
+        else launch2_t<2, 0>(b, d, cf, ty, cz, s);
     }
 }
 

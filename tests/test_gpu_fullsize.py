@@ -1,0 +1,132 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+The terrain block of the benchmark (256^3 voxels, 64 nadir 1024x1024 depth
+maps) is too large for the oracle to solve whole, so it is checked where the
+oracle can follow it exactly:
+
+- histograms: bit-exact against the oracle on random voxels and on whole
+  crops around surface points and block corners;
+- solver: after N iterations a voxel depends only on voxels within Chebyshev
+  distance 2 per iteration (the dual step reads x + e_i, the primal step
+  x - e_i), so a crop that extends 2N + 2 voxels past a sample box on every
+  side (clipped at the block's faces, where the masks are the block's own)
+  gives the oracle exactly the values of the full solve in that box.  The
+  oracle solves the crop from its own histograms; the GPU solves the whole
+  block with the library defaults the benchmark uses;
+- the full 1000-iteration solve of the benchmark, in its tiled launch
+  configuration, is bit-identical to the per-voxel kernels (whose parity
+  with the oracle the small-block tests establish)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+N = 256
+ITERS = 16
+
+
+def say(*a):
+    print("[fullsize]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def terrain():
+    import paper_2107_14790_amd as tgv
+    say("terrain scene 256^3, 64 cameras 1024x1024")
+    sc = scenes.terrain_scene(n=N, n_side=8, W=1024, H=1024, f=1536.0, device="cuda")
+    ctx = tgv.Context(0)
+    H, W = sc.depth.shape[1:]
+    pyr = ctx.build_pyramids(torch.from_numpy(sc.depth).cuda())
+    g = tgv.grid_from(sc.grid)
+    hist = ctx.build_histograms(pyr, W, H, tgv.cameras_from(sc.cams), g)
+    torch.cuda.synchronize()
+    say("oracle pyramids and histograms on 20000 random voxels")
+    opyr = oracle.pyramids(sc.depth)
+    rng = np.random.default_rng(2561)
+    vox = rng.choice(N ** 3, size=20000, replace=False)
+    ref, _ = oracle.histograms(sc, opyr, vox=vox)
+    return dict(ctx=ctx, sc=sc, g=g, hist=hist, opyr=opyr, hist_np=hist.cpu().numpy().view(np.uint16),
+                vox=vox, vox_hist=ref)
+
+
+def crop_box(sample_lo, size, radius):
+    lo = [max(0, s - radius) for s in sample_lo]
+    hi = [min(N, s + size + radius) for s in sample_lo]
+    return lo, hi
+
+
+def crop_scene(sc, lo, hi):
+    g = sc.grid
+    o = np.asarray(g.origin, dtype=np.float64)
+    origin = np.array([o[0] + lo[0] * g.h, o[1] + lo[1] * g.h, o[2] + lo[2] * g.h], dtype=np.float32)
+    shape = tuple(h - l for l, h in zip(lo, hi))
+    return scenes.Scene(sc.depth, sc.cams, scenes.Grid(origin, g.h, shape, 0)), shape
+
+
+def crop_indices(lo, hi):
+    z, y, x = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]), np.arange(lo[0], hi[0]), indexing="ij")
+    return (x + N * y + N * N * z).ravel()
+
+
+def test_histograms_on_random_voxels_bit_exact(terrain):
+    ref = terrain["vox_hist"]
+    assert np.array_equal(terrain["hist_np"][terrain["vox"]], ref)
+    assert ref.sum() > 0
+
+
+def surface_samples(vox, vox_hist, k, rng):
+    """k of the oracle's random voxels with votes in the inner bins (near the surface)."""
+    near = vox[np.nonzero(vox_hist[:, 1:6].sum(axis=1))[0]]
+    idx = rng.choice(near, size=k, replace=False)
+    return [(int(i % N), int((i // N) % N), int(i // (N * N))) for i in idx]
+
+
+def test_solver_crops_match_oracle(terrain):
+    """16 iterations on the whole block (library defaults) against the oracle
+    on crops around 4^3 sample boxes: at surface points, a block corner and
+    an edge."""
+    import paper_2107_14790_amd as tgv
+    ctx, g = terrain["ctx"], terrain["g"]
+    u = torch.zeros(N ** 3, device="cuda")
+    ctx.solve(g, terrain["hist"], u, tgv.Params(iters=ITERS))
+    torch.cuda.synchronize()
+    u_gpu = u.cpu().numpy().reshape(N, N, N)
+    rng = np.random.default_rng(2562)
+    samples = surface_samples(terrain["vox"], terrain["vox_hist"], 3, rng)
+    samples = [tuple(min(max(c - 2, 0), N - 4) for c in s) for s in samples] + [(0, 0, 0), (N - 4, N - 4, 100)]
+    radius = 2 * ITERS + 2
+    for s in samples:
+        lo, hi = crop_box(s, 4, radius)
+        csc, shape = crop_scene(terrain["sc"], lo, hi)
+        say("crop", lo, hi)
+        h_ref, _ = oracle.histograms(csc, terrain["opyr"])
+        assert np.array_equal(terrain["hist_np"][crop_indices(lo, hi)], h_ref), "crop histograms"
+        st = oracle.solve(h_ref, shape, scenes.default_bins(), ITERS)
+        uc = st.u.reshape(shape[2], shape[1], shape[0])
+        a = [s[i] - lo[i] for i in range(3)]
+        ref = uc[a[2]:a[2] + 4, a[1]:a[1] + 4, a[0]:a[0] + 4]
+        got = u_gpu[s[2]:s[2] + 4, s[1]:s[1] + 4, s[0]:s[0] + 4]
+        assert np.abs(got - ref).max() <= 1e-4, s
+
+
+def test_bench_solve_bit_identical_to_per_voxel_kernels(terrain):
+    """The benchmark's 1000 iterations in the tiled launch configuration
+    against the same solve with the per-voxel dual and primal kernels."""
+    import paper_2107_14790_amd as tgv
+    ctx, g = terrain["ctx"], terrain["g"]
+    out = []
+    for sched in (tgv.SCHED_FUSED, tgv.SCHED_SPLIT):
+        say("1000 iterations, schedule", sched)
+        u = torch.zeros(N ** 3, device="cuda")
+        st = ctx.solve(g, terrain["hist"], u, tgv.Params(iters=1000, schedule=sched), stats=True)
+        torch.cuda.synchronize()
+        assert st["nonfinite"] == 0
+        out.append(u.cpu().numpy())
+    assert np.array_equal(out[0].view(np.uint32), out[1].view(np.uint32))

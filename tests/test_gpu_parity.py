@@ -334,6 +334,27 @@ def test_tiled_kernel_bitwise_equals_split(ctx, shape, halo, storage):
             assert np.array_equal(ref[k].view(np.uint32), got[k].view(np.uint32)), (k, ty, cz)
 
 
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_streamed_store_path_bitwise_equals_split(ctx, storage):
+    """A block whose iteration moves more than 256 MiB (160^3: 491 MB in
+    float32, 295 MB in 16-bit storage) takes the non-temporal store path and,
+    in float32, the 64 x 8 default tile; bit-identical to the per-voxel
+    kernels all the same."""
+    import paper_2107_14790_amd as tgv
+    shape = (160, 160, 160)
+    say("streamed stores", shape, storage)
+    rng = np.random.default_rng(160 + storage)
+    n = int(np.prod(shape))
+    hist = np.zeros((n, 8), dtype=np.uint16)
+    hist[:, :7] = rng.integers(0, 3, size=(n, 7), dtype=np.uint16) * (rng.random((n, 1)) < 0.4)
+    u0 = np.where(rng.random(n) < 0.5, rng.uniform(-1, 1, n), 0.0).astype(np.float32)
+    ref = _full_state(ctx, hist, shape, 9, 0, u0, tgv.Params(iters=9, storage=storage, schedule=tgv.SCHED_SPLIT))
+    for ty, cz in [(0, 0), (4, 32)]:
+        got = _full_state(ctx, hist, shape, 9, 0, u0, tgv.Params(iters=9, storage=storage, tile_y=ty, tile_z=cz))
+        for k in ref:
+            assert np.array_equal(ref[k].view(np.uint32), got[k].view(np.uint32)), (k, ty, cz)
+
+
 # ---------------------------------------------------------------------------
 # zero-level points
 # ---------------------------------------------------------------------------
