@@ -222,7 +222,12 @@ tgv_status tgv_state_import(tgv_ctx *ctx, tgv_state *st, const float *u, const f
  * state != NULL: the state is advanced (it must match grid and
  * params->storage) and u is written to u_io when u_io != NULL.
  * stats_host != NULL: also reduce the energy statistics of the final
- * state (this synchronises the stream). */
+ * state (this synchronises the stream).
+ * The gap every k iterations: solve in chunks of k on a state with
+ * stats_host set (resuming is bit-identical to one long solve).
+ * Blocks with 24 * nx * ny * nz >= 2^31 (about 447^3 voxels) exceed the
+ * tiled kernels' 32-bit buffer offsets; their fused passes run the
+ * per-voxel fused kernel (same results, slower). */
 tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
                      const tgv_params *params, float *u_io, tgv_state *state, tgv_stats *stats_host, void *stream);
 

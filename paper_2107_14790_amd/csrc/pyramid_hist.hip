@@ -171,8 +171,12 @@ void launch_fill(float *p, float v, long long n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
 }
 
+// Zero nbytes rounded up to whole 32-bit words: a 16-bit field array of an
+// odd voxel count ends on a half word, and its last element must be cleared
+// too.  Every caller's array is padded to 256 bytes, so the rounding stays
+// inside the allocation.
 void launch_fill_bytes0(void *p, long long nbytes, hipStream_t s) {
-    long long n = nbytes / 4;  // every field array is a multiple of 4 bytes in size
+    long long n = (nbytes + 3) / 4;
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill0_u32, dim3(fill_blocks(n)), dim3(256), 0, s, (uint32_t *)p, n);
 }

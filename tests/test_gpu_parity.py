@@ -313,7 +313,7 @@ def _full_state(ctx, hist_np, shape, iters, halo, u0, params):
 
 
 @pytest.mark.parametrize("shape,halo", [((70, 37, 23), 2), ((130, 20, 67), 0), ((64, 8, 32), 1), ((5, 3, 40), 0),
-                                        ((200, 1, 3), 0)])
+                                        ((200, 1, 3), 0), ((37, 29, 23), 2)])
 @pytest.mark.parametrize("storage", [0, 1, 2])
 def test_tiled_kernel_bitwise_equals_split(ctx, shape, halo, storage):
     import paper_2107_14790_amd as tgv
@@ -353,6 +353,78 @@ def test_streamed_store_path_bitwise_equals_split(ctx, storage):
         got = _full_state(ctx, hist, shape, 9, 0, u0, tgv.Params(iters=9, storage=storage, tile_y=ty, tile_z=cz))
         for k in ref:
             assert np.array_equal(ref[k].view(np.uint32), got[k].view(np.uint32)), (k, ty, cz)
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_state_reset_clears_every_element_of_odd_sized_blocks(ctx, storage):
+    """A state whose memory held NaN: after a reset v, p and q are exactly 0
+    and u is u0, including the last element of 16-bit arrays of an odd voxel
+    count (3 n or 6 n half words)."""
+    import paper_2107_14790_amd as tgv
+    for shape in ((37, 29, 23), (1, 1, 1), (3, 5, 7)):
+        n = int(np.prod(shape))
+        g = tgv.grid_c((0, 0, 0), 1.0, shape, 0)
+        mem = torch.full((tgv.state_bytes(g, storage) // 4,), float("nan"), device="cuda")
+        st = tgv.State(ctx, g, storage, memory=mem)
+        u0 = torch.linspace(-1, 1, n, device="cuda")
+        st.reset(u0)
+        f = st.export()
+        torch.cuda.synchronize()
+        for k in ("v", "v_prev", "p", "q"):
+            assert torch.count_nonzero(f[k]).item() == 0, (shape, k)
+        assert torch.equal(f["u"], u0) and torch.equal(f["u_prev"], u0)
+        st.close()
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_fused_reference_schedule_bitwise_equals_split(ctx, storage):
+    """The per-voxel fused kernel (schedule FUSED_REF, also the path of blocks
+    too large for the tiled kernel's 32-bit offsets) against the split one."""
+    import paper_2107_14790_amd as tgv
+    for shape, halo in (((37, 29, 23), 2), ((130, 9, 5), 0), ((1, 1, 1), 0)):
+        say("fused_ref vs split", shape, halo, storage)
+        rng = np.random.default_rng(sum(shape) + 31 * storage)
+        n = int(np.prod(shape))
+        hist = np.zeros((n, 8), dtype=np.uint16)
+        hist[:, :7] = rng.integers(0, 4, size=(n, 7), dtype=np.uint16) * (rng.random((n, 1)) < 0.5)
+        u0 = np.where(rng.random(n) < 0.5, rng.uniform(-1, 1, n), 0.0).astype(np.float32)
+        ref = _full_state(ctx, hist, shape, 17, halo, u0, tgv.Params(iters=17, storage=storage,
+                                                                    schedule=tgv.SCHED_SPLIT))
+        got = _full_state(ctx, hist, shape, 17, halo, u0, tgv.Params(iters=17, storage=storage,
+                                                                    schedule=tgv.SCHED_FUSED_REF))
+        for k in ref:
+            assert np.array_equal(ref[k].view(np.uint32), got[k].view(np.uint32)), k
+
+
+def test_block_beyond_tiled_offsets_falls_back_correctly(ctx):
+    """448^3 voxels: 24 n >= 2^31, so the fused passes run the per-voxel
+    fused kernel.  Bitwise equal to the split schedule, and equal to the
+    oracle on a corner crop (4 iterations reach at most 2 voxels each)."""
+    import paper_2107_14790_amd as tgv
+    shape = (448, 448, 448)
+    n = int(np.prod(shape))
+    assert 24 * n >= 2 ** 31
+    say("fallback block", shape)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(448)
+    hist = torch.zeros((n, 8), dtype=torch.int16, device="cuda")
+    hist[:, :7] = torch.randint(0, 3, (n, 7), device="cuda", dtype=torch.int16, generator=gen)
+    hist[torch.rand(n, device="cuda", generator=gen) < 0.6] = 0
+    g = tgv.grid_c((0, 0, 0), 1.0, shape, 0)
+    out = []
+    for sched in (tgv.SCHED_FUSED, tgv.SCHED_SPLIT):
+        u = torch.zeros(n, device="cuda")
+        ctx.solve(g, hist, u, tgv.Params(iters=4, schedule=sched))
+        torch.cuda.synchronize()
+        out.append(u.cpu().numpy())
+    assert np.array_equal(out[0].view(np.uint32), out[1].view(np.uint32))
+    c = 14  # corner crop: sample 4^3 at the origin, 2 * 4 + 2 voxels of context
+    hc = hist.view(shape[2], shape[1], shape[0], 8)[:c, :c, :c].contiguous().cpu().numpy()
+    st = oracle.solve(hc.reshape(-1, 8).view(np.uint16), (c, c, c), scenes.default_bins(), 4)
+    ref = st.u.reshape(c, c, c)[:4, :4, :4]
+    got = out[0].reshape(shape[2], shape[1], shape[0])[:4, :4, :4]
+    assert np.abs(got - ref).max() <= 1e-4
+    del hist
 
 
 # ---------------------------------------------------------------------------
