@@ -680,6 +680,13 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             tiles += (long long)((d.nx + 63) / 64) * ((d.ny + ty - 1) / ty) * ((d.nz + cz - 1) / cz);
         }
         if (tiles > (1LL << 30)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: too many tiles");
+        // a captured graph holds the table addresses: drop it before a table moves
+        if ((n > ctx->bt_blocks_cap || tiles > ctx->bt_tiles_cap) && ctx->graph_exec) {
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->side));
+            (void)hipGraphExecDestroy(ctx->graph_exec);
+            ctx->graph_exec = nullptr;
+            ctx->graph_key.clear();
+        }
         if (n > ctx->bt_blocks_cap) {
             (void)hipFree(ctx->bt_blocks_dev);
             (void)hipHostFree(ctx->bt_blocks_host);
@@ -747,7 +754,8 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             // the graph holds two iterations (parity 0 then 1); it is keyed by
             // everything its kernel arguments capture
             char key[256];
-            int kl = snprintf(key, sizeof(key), "%d|%d|%d|%d|%d|", params->storage, ty, nt, grid, nb);
+            int kl = snprintf(key, sizeof(key), "%d|%d|%d|%d|%d|%p|%p|%p|", params->storage, ty, nt, grid, nb,
+                              (void *)ctx->bt_blocks_dev, (void *)ctx->bt_tiles_dev, (void *)ctx->counters);
             std::string k(key, kl);
             k.append((const char *)&cf, sizeof(cf));
             HIP_TRY(ctx, hipEventRecord(ctx->ev_a, s));

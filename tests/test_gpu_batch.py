@@ -118,3 +118,55 @@ def test_batch_matches_oracle_on_small_block(ctx):
     u = s.export()["u"].cpu().numpy().astype(np.float64)
     ref = oracle.solve(hist, shape, scenes.default_bins(), 80, halo=halo, u0=u0.astype(np.float64))
     assert np.abs(u - ref.u).max() <= 1e-4
+
+
+def test_batch_with_block_beyond_tiled_offsets_and_table_growth(ctx):
+    """A graph-replayed batch of one block, then a batch that adds a 448^3
+    block (too large for the tiled kernels' 32-bit offsets: it runs its own
+    per-voxel fused launches) with the same tiled work, which grows the
+    block table under an otherwise identical graph.  Every block's state
+    equals its solo solve bit for bit."""
+    import paper_2107_14790_amd as tgv
+    say("batch with a 448^3 block")
+    shape_s, halo_s, hist_s, u0_s = make_blocks(3)[0]
+    big = (448, 448, 448)
+    nb = int(np.prod(big))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(449)
+    hist_b = torch.zeros((nb, 8), dtype=torch.int16, device="cuda")
+    hist_b[:, :7] = torch.randint(0, 3, (nb, 7), device="cuda", dtype=torch.int16, generator=gen)
+    hist_b[torch.rand(nb, device="cuda", generator=gen) < 0.6] = 0
+    u0_b = torch.zeros(nb, device="cuda")
+    g_s = tgv.grid_c((0, 0, 0), 1.0, shape_s, halo_s)
+    g_b = tgv.grid_c((0, 0, 0), 1.0, big, 0)
+    h_s = torch.from_numpy(hist_s.view(np.int16)).cuda()
+    p = tgv.Params(iters=6, flags=tgv.FLAG_GRAPH)
+
+    def new_state(g, u0):
+        st = tgv.State(ctx, g, 0)
+        st.reset(u0)
+        return st
+
+    a = new_state(g_s, torch.from_numpy(u0_s).cuda())
+    ctx.solve_batch([a], [h_s], p)  # captures the graph with a one-block table
+    b_small = new_state(g_s, torch.from_numpy(u0_s).cuda())
+    b_big = new_state(g_b, u0_b)
+    ctx.solve_batch([b_small, b_big], [h_s, hist_b], p)  # same tiled work, larger table
+    torch.cuda.synchronize()
+    solo_s = new_state(g_s, torch.from_numpy(u0_s).cuda())
+    ctx.solve(g_s, h_s, None, tgv.Params(iters=6), state=solo_s)
+    solo_b = new_state(g_b, u0_b)
+    ctx.solve(g_b, hist_b, None, tgv.Params(iters=6), state=solo_b)
+    torch.cuda.synchronize()
+    fa, fs = fields(a), fields(solo_s)
+    for k in fa:
+        assert np.array_equal(fa[k], fs[k]), ("first batch", k)
+    fb = fields(b_small)
+    for k in fb:
+        assert np.array_equal(fb[k], fs[k]), ("second batch, small block", k)
+    xb, yb = b_big.export(), solo_b.export()
+    for k in xb:
+        assert torch.equal(xb[k], yb[k]), ("second batch, 448^3 block", k)
+    del xb, yb
+    for st in (a, b_small, b_big, solo_s, solo_b):
+        st.close()
