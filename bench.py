@@ -257,7 +257,7 @@ def bench_block(args):
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
-        cpu = cpu_baseline(sc, bins.centers32(), crop=min(64, n), iters_sample=150 if n >= 64 else 600)
+        cpu = cpu_baseline(sc, bins.centers32(), crop=min(96, n), iters_sample=200 if n >= 64 else 600)
         cpu.pop("hist_pairs_per_s", None)
 
     lat_ms = sorted(1000.0 * x for x in lat)
