@@ -90,7 +90,7 @@ enum { TGV_STORE_F32 = 0, TGV_STORE_F16 = 1, TGV_STORE_BF16 = 2 };
  * and the primal update as two per-voxel kernels; FUSED_REF runs the fused
  * iteration as a per-voxel kernel; FUSED2 runs two fused iterations per
  * pass over memory (temporal blocking: the second iteration consumes the
- * first one's results from registers and LDS; tile_y in {4, 6}, default
+ * first one's results from registers and LDS; tile_y in {4, 6, 7}, default
  * 64 x 6 x 64 tiles).  All four produce bit-identical results.  The batched
  * solve treats FUSED2 as FUSED. */
 enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1, TGV_SCHED_FUSED_REF = 2, TGV_SCHED_FUSED2 = 3 };
@@ -101,7 +101,7 @@ enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1, TGV_SCHED_FUSED_REF = 2, TGV_SC
  * workgroup); 0 picks the library default: 64 x 8 x 32 for a float32
  * block whose iteration moves more than 256 MiB, else 64 x 4 x 32;
  * 64 x 6 x 64 for FUSED2; 64 x 4 for a batched solve (tile_y in {4, 8, 12};
- * in {4, 6} for FUSED2). */
+ * in {4, 6, 7} for FUSED2). */
 typedef struct {
     float alpha0, alpha1, lambda;
     float tau, sigma;

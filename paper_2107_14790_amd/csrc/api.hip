@@ -136,6 +136,8 @@ extern "C" tgv_status tgv_create(int device, tgv_ctx **out) {
     if (hipSetDevice(device) != hipSuccess) return TGV_E_DEVICE;
     tgv_ctx *c = new tgv_ctx();
     c->device = device;
+    c->cus = 256;
+    (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
     c->cams_host = nullptr;
     c->cams_dev = nullptr;
     c->cams_cap = 0;
@@ -583,7 +585,8 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
                 // written, which only the final primal pass could notice,
                 // and it overwrites that buffer
                 const int ty2 = params->tile_y ? params->tile_y : DEFAULT_TILE2_Y;
-                const int cz2 = params->tile_z ? params->tile_z : DEFAULT_TILE2_Z;
+                const int cz2 = params->tile_z ? params->tile_z
+                                               : choose_tile2_z(d, ty2, ctx->cus * tiled2_blocks_per_cu(st->storage, ty2));
                 for (; it + 2 < N; it += 2) {
                     launch_tiled2(st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, ty2, cz2, s);
                     st->xc ^= 1;
@@ -615,13 +618,9 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
 // ===========================================================================
 // batched solve
 // ===========================================================================
-static int persistent_grid(tgv_ctx *ctx, int ty, int ntiles) {
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-    // workgroups per CU the tiled kernel sustains (VGPR- and LDS-limited): 7-wave
-    // groups fit 3 per CU, 11-wave groups 2, 15-wave groups 1
-    int per_cu = ty == 4 ? 3 : (ty == 8 ? 2 : 1);
-    int g = cus * per_cu;
+static int persistent_grid(tgv_ctx *ctx, int storage, int ty, int ntiles) {
+    // as many workgroups as can be resident at once (occupancy of the batched kernel)
+    int g = ctx->cus * batch_blocks_per_cu(storage, ty);
     g = (g + 7) / 8 * 8;
     int cap = (ntiles + 7) / 8 * 8;
     return g < cap ? g : cap;
@@ -742,7 +741,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
         HIP_TRY(ctx, hipEventRecord(ctx->bt_evt, s));
     }
     // 3. N-1 fused iterations of all blocks: one persistent launch each
-    const int grid = persistent_grid(ctx, ty, nt);
+    const int grid = persistent_grid(ctx, params->storage, ty, nt);
     const int F = N - 1;
     if (nb > 0 && F > 0) {
         const bool use_graph = (params->flags & TGV_FLAG_GRAPH) && F >= 2;

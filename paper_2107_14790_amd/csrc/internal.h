@@ -91,14 +91,18 @@ inline bool stream_stores(int storage, const Dims &d) {
 // Default tiles (measured): 64 x 8 x 32 for a float32 block larger than the
 // infinity cache (256^3: 5 % faster than 64 x 4), else 64 x 4 x 32 (city
 // blocks: 3 % faster than 64 x 8; 16-bit storage at 256^3: 64 x 4 is
-// fastest); FUSED2 64 x 6 x 64; the batched solve defaults to 64 x 4.
+// fastest); FUSED2 64 x 7 (twelve waves: one workgroup fills a CU's three
+// waves per SIMD) with the chunk depth from choose_tile2_z; the batched
+// solve defaults to 64 x 4.
 constexpr int DEFAULT_TILE_Z = 32;
 constexpr int DEFAULT_BATCH_TILE_Y = 4;
-constexpr int DEFAULT_TILE2_Y = 6;
-constexpr int DEFAULT_TILE2_Z = 64;
+constexpr int DEFAULT_TILE2_Y = 7;
 inline int default_tile_y(int storage, const Dims &d) { return (storage == 0 && stream_stores(storage, d)) ? 8 : 4; }
-// two fused iterations per launch (temporal blocking), tiles 64 x ty (ty in {4, 6})
+// two fused iterations per launch (temporal blocking), tiles 64 x ty (ty in {4, 6, 7})
 bool tiled2_shape_ok(int ty, int cz);
+int tiled2_blocks_per_cu(int storage, int ty);
+int choose_tile2_z(const Dims &d, int ty, int slots);
+int batch_blocks_per_cu(int storage, int ty);
 void launch_tiled2(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);
 // one fused iteration of every block listed in `tiles` (int4: block, tix | tiy << 16, tiz, 0)
 void launch_batch(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
@@ -123,6 +127,7 @@ void launch_extract(const float *u, const Dims &d, const tgv_grid &g, unsigned *
 
 struct tgv_ctx {
     int device;
+    int cus;  // compute units of the device
     std::string err;
     // pinned staging for the camera table + its device copy
     tgv::CamDev *cams_host;

@@ -438,6 +438,21 @@ static void launch_batch_t(const BatchBlock *blocks, const int4 *tiles, int ntil
                            counters, cf, flip);
 }
 
+// resident workgroups per CU of the batched kernel (registers and LDS)
+template <int STORE, int TY>
+static int batch_per_cu_t() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused_batch<STORE, TY>, TX * (TY + 3), 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int batch_blocks_per_cu(int storage, int ty) {
+    if (storage == 0) return ty == 4 ? batch_per_cu_t<0, 4>() : (ty == 12 ? batch_per_cu_t<0, 12>() : batch_per_cu_t<0, 8>());
+    if (storage == 1) return ty == 4 ? batch_per_cu_t<1, 4>() : (ty == 12 ? batch_per_cu_t<1, 12>() : batch_per_cu_t<1, 8>());
+    return ty == 4 ? batch_per_cu_t<2, 4>() : (ty == 12 ? batch_per_cu_t<2, 12>() : batch_per_cu_t<2, 8>());
+}
+
 void launch_batch(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
                   int ty, int flip, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters);

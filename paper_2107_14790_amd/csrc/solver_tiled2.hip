@@ -356,10 +356,8 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
         if (runA) primal(la, A, Acur, Aprev, hA, s);
         if (runB) primal(lb, B, Bcur, Bprev, hD2, sb);
         lds_barrier2();
-        // phase 3
-        Pl res;
-        bool madeA = false;
-        if (runA) madeA = dual(la, A, Aprev, s, res);
+        // phase 3 (stage B first: its previous plane is dead before stage A's
+        // result, which takes its place, is formed)
         if (runB) {
             Pl outB;
             if (dual(lb, B, Bprev, sb, outB) && in) {
@@ -371,6 +369,9 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
                 for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, oS + c * comp, outB.q[c]);
             }
         }
+        Pl res;
+        bool madeA = false;
+        if (runA) madeA = dual(la, A, Aprev, s, res);
         // rotate: stage A's result for plane s-1 becomes stage B's newest plane
         if (runA) Aprev = Acur;
         Bprev = Bcur;
@@ -403,10 +404,51 @@ static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz
 template <int STORE, int SCP>
 static void launch2_t(const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
     if (ty == 6) launch2_ty<STORE, 6, SCP>(b, d, cf, cz, s);
+    else if (ty == 7) launch2_ty<STORE, 7, SCP>(b, d, cf, cz, s);
     else launch2_ty<STORE, 4, SCP>(b, d, cf, cz, s);
 }
 
-bool tiled2_shape_ok(int ty, int cz) { return (ty == 4 || ty == 6) && cz >= 1; }
+bool tiled2_shape_ok(int ty, int cz) { return (ty == 4 || ty == 6 || ty == 7) && cz >= 1; }
+
+// resident workgroups per CU of the two-iteration kernel
+template <int STORE, int TY>
+static int per_cu2_t() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused2_tiled<STORE, TY, STORE_CP_STREAM>, TX * (TY + 5),
+                                                     0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int tiled2_blocks_per_cu(int storage, int ty) {
+    if (storage == 0) return ty == 4 ? per_cu2_t<0, 4>() : (ty == 6 ? per_cu2_t<0, 6>() : per_cu2_t<0, 7>());
+    if (storage == 1) return ty == 4 ? per_cu2_t<1, 4>() : (ty == 6 ? per_cu2_t<1, 6>() : per_cu2_t<1, 7>());
+    return ty == 4 ? per_cu2_t<2, 4>() : (ty == 6 ? per_cu2_t<2, 6>() : per_cu2_t<2, 7>());
+}
+
+// Planes per z-chunk: a launch runs ceil(tiles / slots) rounds of resident
+// workgroups, and a tile of cz planes takes cz + 3 plane steps (the two
+// stages' pipeline fill and the z-halo), so the chunk minimising
+// rounds x (cz + 3) is taken (ties: the deeper chunk).  On a 256^3 block with
+// 64 x 7 tiles and 256 slots this picks 52 planes (740 tiles in three nearly
+// full rounds); the model's ratios for 64 and 26 planes (1.22, 1.06) match
+// the measured times (1.20, 1.05).
+int choose_tile2_z(const Dims &d, int ty, int slots) {
+    const long long per_chunk = (long long)((d.nx + TX - 1) / TX) * ((d.ny + ty - 1) / ty);
+    const int lo = d.nz < 8 ? d.nz : 8;
+    long long best = -1;
+    int best_cz = d.nz;
+    for (int cz = d.nz; cz >= lo; cz--) {
+        const long long tiles = per_chunk * ((d.nz + cz - 1) / cz);
+        const long long rounds = (tiles + slots - 1) / slots;
+        const long long cost = rounds * (cz + 3);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_cz = cz;
+        }
+    }
+    return best_cz;
+}
 
 void launch_tiled2(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
     if (stream_stores(storage, d)) {

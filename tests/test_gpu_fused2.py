@@ -72,6 +72,8 @@ CASES = [
     ((17, 1, 1), 0, 8, 4, 2),
     ((1, 13, 6), 0, 7, 6, 3),
     ((3, 2, 2), 0, 3, 4, 1),
+    ((100, 45, 33), 1, 9, 7, 13),
+    ((64, 7, 20), 0, 6, 7, 64),
 ]
 
 
