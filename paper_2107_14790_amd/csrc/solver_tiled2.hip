@@ -326,41 +326,49 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     // plane s-1.  Stage B walks one step later than it could, at plane
     // sb = s - 2, so both stages share the two barriers of a step: its
     // (prev, cur) are stage A's results for planes s-3 and s-2, and the
-    // histogram of plane s-2 comes down a two-step register delay line.
-    Pl Aprev, Acur, Anext, Bcur, Bprev;
-    uint32_t hA[4], hAn[4], hD1[4], hD2[4];
-    Aprev.u = 0.0f;
-    for (int c = 0; c < 3; c++) Aprev.p[c] = Aprev.v[c] = 0.0f;
-    for (int c = 0; c < 6; c++) Aprev.q[c] = 0.0f;
-    Bcur = Aprev;
-    Bprev = Aprev;
-    for (int c = 0; c < 4; c++) hD1[c] = hD2[c] = 0u;
+    // histogram of plane s-2 is kept from stage A's plane s-2.  Both stages
+    // keep three plane slots that rotate by one per step; the loop is
+    // unrolled three times so the rotation is a renaming, not a copy, and
+    // stage A writes its result into the slot stage B has just finished.
+    struct PlH {
+        Pl f;
+        uint32_t h[4];
+    };
+    PlH a0, a1, a2;
+    Pl b0, b1, b2;
+    uint32_t hB[4] = {0u, 0u, 0u, 0u};
+    a0.f.u = 0.0f;
+    for (int c = 0; c < 3; c++) a0.f.p[c] = a0.f.v[c] = 0.0f;
+    for (int c = 0; c < 6; c++) a0.f.q[c] = 0.0f;
+    for (int c = 0; c < 4; c++) a0.h[c] = 0u;
+    b0 = a0.f;
+    b1 = a0.f;
+    b2 = a0.f;
     const int sA0 = max(A.z0 - 1, 0), sA1 = A.zl + 1;
     const int sB0 = max(B.z0 - 1, 0), sB1 = B.zl + 1;
     const int s_end = sB1 + 2;
-    load_state(Anext, hAn, sA0);
-    for (int s = sA0; s <= s_end; s++) {
+    load_state(a1.f, a1.h, sA0);
+
+    // one plane step: stage A on (prev, cur, next) = (ap, ac, an), stage B on
+    // (prev, cur) = (bp, bc), stage A's result into bo
+    auto step = [&](PlH &ap, PlH &ac, PlH &an, Pl &bp, Pl &bc, Pl &bo, int s) {
         const bool runA = s <= sA1;
         const int sb = s - 2;
         const bool runB = sb >= sB0;
-        if (runA) {
-            Acur = Anext;
-            for (int c = 0; c < 4; c++) hA[c] = hAn[c];
-            if (s + 1 <= sA1) load_state(Anext, hAn, s + 1);
-        }
+        if (runA && s + 1 <= sA1) load_state(an.f, an.h, s + 1);
         // phase 1
-        if (runA) publish(la, A, Acur, Aprev);
-        if (runB) publish(lb, B, Bcur, Bprev);
+        if (runA) publish(la, A, ac.f, ap.f);
+        if (runB) publish(lb, B, bc, bp);
         lds_barrier2();
         // phase 2
-        if (runA) primal(la, A, Acur, Aprev, hA, s);
-        if (runB) primal(lb, B, Bcur, Bprev, hD2, sb);
+        if (runA) primal(la, A, ac.f, ap.f, ac.h, s);
+        if (runB) primal(lb, B, bc, bp, hB, sb);
         lds_barrier2();
         // phase 3 (stage B first: its previous plane is dead before stage A's
-        // result, which takes its place, is formed)
+        // result, which takes its slot two steps later, is formed)
         if (runB) {
             Pl outB;
-            if (dual(lb, B, Bprev, sb, outB) && in) {
+            if (dual(lb, B, bp, sb, outB) && in) {
                 const int sv = sb - 1;
                 const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
                 Io2<0>::st<SCP>(wu, v4, o4, outB.u);
@@ -369,22 +377,16 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
                 for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, oS + c * comp, outB.q[c]);
             }
         }
-        Pl res;
-        bool madeA = false;
-        if (runA) madeA = dual(la, A, Aprev, s, res);
-        // rotate: stage A's result for plane s-1 becomes stage B's newest plane
-        if (runA) Aprev = Acur;
-        Bprev = Bcur;
-        if (madeA) Bcur = res;
-        else {
-            Bcur.u = 0.0f;
-            for (int c = 0; c < 3; c++) Bcur.v[c] = Bcur.p[c] = 0.0f;
-            for (int c = 0; c < 6; c++) Bcur.q[c] = 0.0f;
-        }
-        for (int c = 0; c < 4; c++) {
-            hD2[c] = hD1[c];
-            hD1[c] = hA[c];
-        }
+        if (runA) dual(la, A, ap.f, s, bo);
+        // the histogram of plane s-1 serves stage B at the next step
+        for (int c = 0; c < 4; c++) hB[c] = ap.h[c];
+    };
+    for (int s = sA0; s <= s_end; s += 3) {
+        step(a0, a1, a2, b0, b1, b2, s);
+        if (s + 1 > s_end) break;
+        step(a1, a2, a0, b1, b2, b0, s + 1);
+        if (s + 2 > s_end) break;
+        step(a2, a0, a1, b2, b0, b1, s + 2);
     }
 }
 
@@ -420,10 +422,13 @@ static int per_cu2_t() {
     return nb > 0 ? nb : 1;
 }
 
+template <int STORE>
+static int per_cu2_s(int ty) {
+    return ty == 4 ? per_cu2_t<STORE, 4>() : (ty == 6 ? per_cu2_t<STORE, 6>() : per_cu2_t<STORE, 7>());
+}
+
 int tiled2_blocks_per_cu(int storage, int ty) {
-    if (storage == 0) return ty == 4 ? per_cu2_t<0, 4>() : (ty == 6 ? per_cu2_t<0, 6>() : per_cu2_t<0, 7>());
-    if (storage == 1) return ty == 4 ? per_cu2_t<1, 4>() : (ty == 6 ? per_cu2_t<1, 6>() : per_cu2_t<1, 7>());
-    return ty == 4 ? per_cu2_t<2, 4>() : (ty == 6 ? per_cu2_t<2, 6>() : per_cu2_t<2, 7>());
+    return storage == 0 ? per_cu2_s<0>(ty) : (storage == 1 ? per_cu2_s<1>(ty) : per_cu2_s<2>(ty));
 }
 
 // Planes per z-chunk: a launch runs ceil(tiles / slots) rounds of resident

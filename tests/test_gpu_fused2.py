@@ -74,6 +74,7 @@ CASES = [
     ((3, 2, 2), 0, 3, 4, 1),
     ((100, 45, 33), 1, 9, 7, 13),
     ((64, 7, 20), 0, 6, 7, 64),
+    ((130, 50, 41), 2, 10, 7, 9),
 ]
 
 
