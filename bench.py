@@ -532,6 +532,7 @@ def bench_city_precision(args):
 
     iters = args.iters or 1000
     n = args.n if args.n != 256 else 384
+    sched = tgv.SCHED_FUSED2 if args.schedule == "fused2" else tgv.SCHED_FUSED
     if not os.path.exists(scenes._RAYLIB):
         scenes.build_raycaster()
     t0 = time.perf_counter()
@@ -553,10 +554,10 @@ def bench_city_precision(args):
         st = tgv.STORAGE_NAMES[name]
         u = torch.zeros(nvox, device="cuda")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ctx.solve(g, hist, u, tgv.Params(iters=5, storage=st))  # warm
+        ctx.solve(g, hist, u, tgv.Params(iters=5, storage=st, schedule=sched))  # warm
         u.zero_()
         e0.record(s)
-        stats = ctx.solve(g, hist, u, tgv.Params(iters=iters, storage=st))
+        stats = ctx.solve(g, hist, u, tgv.Params(iters=iters, storage=st, schedule=sched))
         e1.record(s)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -584,7 +585,7 @@ def bench_city_precision(args):
     vs64 = {}
     for name in ("f32", "f16", "bf16"):
         u = torch.zeros(m ** 3, device="cuda")
-        ctx.solve(gs, hs, u, tgv.Params(iters=iters, storage=tgv.STORAGE_NAMES[name]))
+        ctx.solve(gs, hs, u, tgv.Params(iters=iters, storage=tgv.STORAGE_NAMES[name], schedule=sched))
         torch.cuda.synchronize()
         vs64[name] = zero_crossing_errors(u, uref, (m, m, m))
         vs64[name]["max_abs"] = float((u.double() - uref).abs().max().item())
@@ -598,7 +599,7 @@ def bench_city_precision(args):
         "dtype": "f32 compute, f16 storage (value); f32 and bf16 storage reported beside",
         "data": "synthetic",
         "config": {"workload": "city_precision", "grid": [n, n, n], "cameras": len(sc.cams), "image": [W, H],
-                   "iters": iters, "h": h},
+                   "iters": iters, "h": h, "schedule": args.schedule},
         "storage": res,
         "vs_float64_oracle_64cube": vs64,
     }

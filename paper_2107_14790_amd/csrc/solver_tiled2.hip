@@ -49,6 +49,10 @@ struct Io2<0> {
 };
 template <>
 struct Io2<1> {
+    static __device__ __forceinline__ uint32_t raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    }
+    static __device__ __forceinline__ float cvt(uint32_t b) { return __half2float(__ushort_as_half((unsigned short)b)); }
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
     }
@@ -59,6 +63,10 @@ struct Io2<1> {
 };
 template <>
 struct Io2<2> {
+    static __device__ __forceinline__ uint32_t raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    }
+    static __device__ __forceinline__ float cvt(uint32_t b) { return __uint_as_float(b << 16); }
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
         return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)) << 16);
     }
@@ -90,6 +98,11 @@ constexpr int LD2_SKIP = (int)0x80000000u;  // >= every buffer's size (below 2^3
 // the state of one column at one plane
 struct Pl {
     float u, v[3], p[3], q[6];
+};
+
+// a plane of 16-bit fields as loaded (bits), converted when it is used
+struct PlRaw {
+    uint32_t u, v[3], p[3], q[6];
 };
 
 __device__ __forceinline__ int lq2(int slot) { return slot == 0 ? 0 : (slot == 1 ? 1 : slot - 1); }
@@ -173,7 +186,10 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     }
     const bool active = kind >= 0;
     const bool in = active && px >= 0 && py >= 0 && px < d.nx && py < d.ny;
-    const int lmask = in ? lm : 0;
+    // 16-bit fields: every lane loads every field (lanes outside the block
+    // read column 0, as in the one-iteration kernel); masked-off 16-bit loads
+    // made both kernels slower
+    const int lmask = STORE == 0 ? (in ? lm : 0) : LD2_ALL;
     const int e = active ? (py - y0 + 2) * EX + (px - x0 + 2) : 0;
     const bool mlo_x = px > 0, mlo_y = py > 0, mhi_x = px < d.nx - 1, mhi_y = py < d.ny - 1;
     const bool fxy = d.halo > 0 && (px < d.halo || py < d.halo || px >= d.nx - d.halo || py >= d.ny - d.halo);
@@ -230,6 +246,32 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
         hw[2] = hv[2];
         hw[3] = hv[3];
     };
+    // 16-bit storage: load the plane's bits now, convert them a step later
+    // (converting at the load would wait for it and stall the prefetch)
+    auto load_raw = [&](PlRaw &R, uint32_t hw[4], int s) {
+        const int sc = s < d.nz ? s : d.nz - 1;
+        const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
+        const int m = lmask;
+        R.u = __builtin_amdgcn_raw_buffer_load_b32(ru, (m & LD2_U) ? v4 : LD2_SKIP, o4, 0);
+        const int ov = (m & LD2_V) ? vS : LD2_SKIP;
+        for (int c = 0; c < 3; c++) R.v[c] = Io2<STORE == 0 ? 1 : STORE>::raw(rv, ov, oS + c * comp);
+        for (int c = 0; c < 3; c++)
+            R.p[c] = Io2<STORE == 0 ? 1 : STORE>::raw(rp, (m & (LD2_PX << c)) ? vS : LD2_SKIP, oS + c * comp);
+        for (int c = 0; c < 6; c++)
+            R.q[c] = Io2<STORE == 0 ? 1 : STORE>::raw(rq, (m & (LD2_Q0 << c)) ? vS : LD2_SKIP, oS + c * comp);
+        auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, (m & LD2_H) ? vH : LD2_SKIP, oH, 0);
+        hw[0] = hv[0];
+        hw[1] = hv[1];
+        hw[2] = hv[2];
+        hw[3] = hv[3];
+    };
+    auto convert = [&](const PlRaw &R, Pl &P) {
+        P.u = __uint_as_float(R.u);
+        for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(R.v[c]);
+        for (int c = 0; c < 3; c++) P.p[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(R.p[c]);
+        for (int c = 0; c < 6; c++) P.q[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(R.q[c]);
+    };
+
     // phase 1: publish p_x, p_y of plane s (cur) and q of plane s-1 (prev)
     auto publish = [&](L &l, const Stage &S, const Pl &cur, const Pl &prev) {
         if (S.active) {
@@ -347,7 +389,9 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     const int sA0 = max(A.z0 - 1, 0), sA1 = A.zl + 1;
     const int sB0 = max(B.z0 - 1, 0), sB1 = B.zl + 1;
     const int s_end = sB1 + 2;
-    load_state(a1.f, a1.h, sA0);
+    PlRaw R;  // 16-bit storage: the plane in flight
+    if (STORE == 0) load_state(a1.f, a1.h, sA0);
+    else load_raw(R, a1.h, sA0);
 
     // one plane step: stage A on (prev, cur, next) = (ap, ac, an), stage B on
     // (prev, cur) = (bp, bc), stage A's result into bo
@@ -355,7 +399,12 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
         const bool runA = s <= sA1;
         const int sb = s - 2;
         const bool runB = sb >= sB0;
-        if (runA && s + 1 <= sA1) load_state(an.f, an.h, s + 1);
+        if (STORE == 0) {
+            if (runA && s + 1 <= sA1) load_state(an.f, an.h, s + 1);
+        } else {
+            if (runA) convert(R, ac.f);
+            if (runA && s + 1 <= sA1) load_raw(R, an.h, s + 1);
+        }
         // phase 1
         if (runA) publish(la, A, ac.f, ap.f);
         if (runB) publish(lb, B, bc, bp);
