@@ -91,9 +91,12 @@ enum { TGV_STORE_F32 = 0, TGV_STORE_F16 = 1, TGV_STORE_BF16 = 2 };
  * iteration as a per-voxel kernel; FUSED2 runs two fused iterations per
  * pass over memory (temporal blocking: the second iteration consumes the
  * first one's results from registers and LDS; tile_y in {4, 6, 7}, default
- * 64 x 6 x 64 tiles).  All four produce bit-identical results.  The batched
- * solve treats FUSED2 as FUSED. */
-enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1, TGV_SCHED_FUSED_REF = 2, TGV_SCHED_FUSED2 = 3 };
+ * 64 x 7 tiles with the chunk depth chosen for the device); AUTO runs FUSED2
+ * for a block whose iteration moves more than 256 MiB (when tile_y is 0)
+ * and FUSED otherwise.  All of them produce bit-identical results.  A
+ * batched solve always runs its persistent one-iteration kernel, whatever
+ * the schedule. */
+enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1, TGV_SCHED_FUSED_REF = 2, TGV_SCHED_FUSED2 = 3, TGV_SCHED_AUTO = 4 };
 
 /* Solver parameters (Eq. 2, Sec. 3.2).  tau, sigma: primal and dual step
  * sizes (> 0); iters >= 0 primal-dual iterations.  tile_y, tile_z: shape of

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtgv.so")
 
 TGV_OK, TGV_E_INVAL, TGV_E_NOMEM, TGV_E_DEVICE, TGV_E_OVERFLOW, TGV_E_UNSUPPORTED = range(6)
 STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
-SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF, SCHED_FUSED2 = 0, 1, 2, 3
+SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF, SCHED_FUSED2, SCHED_AUTO = 0, 1, 2, 3, 4
 FLAG_GRAPH = 1
 FLAG_TVL1 = 2
 STORAGE_NAMES = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
@@ -186,7 +186,7 @@ class Params:
     sigma: float = float(1.0 / np.sqrt(12.0))
     iters: int = 300
     storage: int = STORE_F32
-    schedule: int = SCHED_FUSED
+    schedule: int = SCHED_AUTO
     tile_y: int = 0
     tile_z: int = 0
     flags: int = 0

@@ -69,9 +69,7 @@ bool params_ok(const tgv_params *p) {
     if (!isfinite(p->alpha0) || !isfinite(p->alpha1) || !isfinite(p->lambda)) return false;
     if (p->iters < 0) return false;
     if (p->storage < 0 || p->storage > 2) return false;
-    if (p->schedule != TGV_SCHED_FUSED && p->schedule != TGV_SCHED_SPLIT && p->schedule != TGV_SCHED_FUSED_REF &&
-        p->schedule != TGV_SCHED_FUSED2)
-        return false;
+    if (p->schedule < TGV_SCHED_FUSED || p->schedule > TGV_SCHED_AUTO) return false;
     if (p->tile_y < 0 || p->tile_z < 0) return false;
     if (p->flags & ~(TGV_FLAG_GRAPH | TGV_FLAG_TVL1)) return false;
     if (p->tile_y != 0) {
@@ -570,7 +568,11 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
             }
             launch_ref(KIND_DUAL, st->storage, b, d, cf, s);
         }
-        if (params->schedule == TGV_SCHED_SPLIT) {
+        // AUTO: two iterations per pass where the block is large, else one
+        int sched = params->schedule;
+        if (sched == TGV_SCHED_AUTO)
+            sched = (params->tile_y == 0 && stream_stores(st->storage, d)) ? TGV_SCHED_FUSED2 : TGV_SCHED_FUSED;
+        if (sched == TGV_SCHED_SPLIT) {
             for (int it = 0; it < N; it++) {
                 if (it > 0) launch_ref(KIND_DUAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
                 launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
@@ -580,7 +582,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
             int ty = params->tile_y ? params->tile_y : default_tile_y(st->storage, d);
             int cz = params->tile_z ? params->tile_z : DEFAULT_TILE_Z;
             int it = 0;
-            if (params->schedule == TGV_SCHED_FUSED2 && tiled_fits(d)) {
+            if (sched == TGV_SCHED_FUSED2 && tiled_fits(d)) {
                 // pairs of fused iterations in one pass; x^{n+1} is never
                 // written, which only the final primal pass could notice,
                 // and it overwrites that buffer
@@ -596,7 +598,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
             }
             for (; it + 1 < N; it++) {
                 SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
-                if (params->schedule == TGV_SCHED_FUSED_REF) launch_ref(KIND_FUSED, st->storage, b, d, cf, s);
+                if (sched == TGV_SCHED_FUSED_REF) launch_ref(KIND_FUSED, st->storage, b, d, cf, s);
                 else launch_tiled(st->storage, b, d, cf, ty, cz, s);
                 st->xc ^= 1;
                 st->yc ^= 1;

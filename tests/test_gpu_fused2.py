@@ -83,7 +83,7 @@ def test_fused2_state_bit_identical(ctx, shape, halo, iters, ty, cz):
     import paper_2107_14790_amd as tgv
     say("shape", shape, "halo", halo, "iters", iters, "tile", ty, cz)
     hist, u0 = random_problem(shape, sum(shape) * 7 + iters)
-    ref = run(ctx, shape, hist, u0, halo, tgv.Params(iters=iters))
+    ref = run(ctx, shape, hist, u0, halo, tgv.Params(iters=iters, schedule=tgv.SCHED_FUSED))
     got = run(ctx, shape, hist, u0, halo, tgv.Params(iters=iters, schedule=tgv.SCHED_FUSED2, tile_y=ty, tile_z=cz))
     assert_same_state(ref, got)
 
@@ -94,7 +94,7 @@ def test_fused2_low_precision_storage_bit_identical(ctx, storage):
     shape = (100, 19, 33)
     say("storage", storage, shape)
     hist, u0 = random_problem(shape, 11 + storage)
-    ref = run(ctx, shape, hist, u0, 1, tgv.Params(iters=11, storage=storage))
+    ref = run(ctx, shape, hist, u0, 1, tgv.Params(iters=11, storage=storage, schedule=tgv.SCHED_FUSED))
     got = run(ctx, shape, hist, u0, 1, tgv.Params(iters=11, storage=storage, schedule=tgv.SCHED_FUSED2, tile_z=6))
     assert_same_state(ref, got)
 
@@ -104,7 +104,7 @@ def test_fused2_tvl1_bit_identical(ctx):
     shape = (70, 30, 18)
     say("tvl1", shape)
     hist, u0 = random_problem(shape, 5)
-    ref = run(ctx, shape, hist, u0, 0, tgv.Params(iters=10, flags=tgv.FLAG_TVL1))
+    ref = run(ctx, shape, hist, u0, 0, tgv.Params(iters=10, flags=tgv.FLAG_TVL1, schedule=tgv.SCHED_FUSED))
     got = run(ctx, shape, hist, u0, 0, tgv.Params(iters=10, flags=tgv.FLAG_TVL1, schedule=tgv.SCHED_FUSED2,
                                                    tile_y=6, tile_z=4))
     assert_same_state(ref, got)
@@ -120,8 +120,9 @@ def test_fused2_rejects_unsupported_tile(ctx):
 
 
 def test_fused2_terrain256_sampled_state(ctx):
-    """The bench's block (256^3) in the bench's launch shape: the default
-    schedule and FUSED2 agree bit for bit on the whole state."""
+    """The bench's block (256^3) in the bench's launch shape: one and two
+    iterations per pass (and the default schedule, which picks the latter
+    at this size) agree bit for bit on the whole state."""
     import paper_2107_14790_amd as tgv
     shape = (256, 256, 256)
     say("256^3 default tiles")
@@ -130,6 +131,8 @@ def test_fused2_terrain256_sampled_state(ctx):
     hist = np.zeros((n, 8), dtype=np.uint16)
     hist[:, :7] = rng.integers(0, 3, size=(n, 7), dtype=np.uint16) * (rng.random((n, 1)) < 0.3)
     u0 = np.zeros(n, np.float32)
-    ref = run(ctx, shape, hist, u0, 0, tgv.Params(iters=7))
+    ref = run(ctx, shape, hist, u0, 0, tgv.Params(iters=7, schedule=tgv.SCHED_FUSED))
     got = run(ctx, shape, hist, u0, 0, tgv.Params(iters=7, schedule=tgv.SCHED_FUSED2))
+    auto = run(ctx, shape, hist, u0, 0, tgv.Params(iters=7))  # the default picks FUSED2 here
+    assert_same_state(ref, auto)
     assert_same_state(ref, got)

@@ -350,7 +350,8 @@ def test_streamed_store_path_bitwise_equals_split(ctx, storage):
     u0 = np.where(rng.random(n) < 0.5, rng.uniform(-1, 1, n), 0.0).astype(np.float32)
     ref = _full_state(ctx, hist, shape, 9, 0, u0, tgv.Params(iters=9, storage=storage, schedule=tgv.SCHED_SPLIT))
     for ty, cz in [(0, 0), (4, 32)]:
-        got = _full_state(ctx, hist, shape, 9, 0, u0, tgv.Params(iters=9, storage=storage, tile_y=ty, tile_z=cz))
+        got = _full_state(ctx, hist, shape, 9, 0, u0, tgv.Params(iters=9, storage=storage, tile_y=ty, tile_z=cz,
+                                                                schedule=tgv.SCHED_FUSED))
         for k in ref:
             assert np.array_equal(ref[k].view(np.uint32), got[k].view(np.uint32)), (k, ty, cz)
 
