@@ -309,9 +309,11 @@ def bench_block(args):
 
 def bench_city_batch(args):
     """512 octree-leaf-like blocks of the city (edges log-uniform 32..128 plus a
-    2-voxel halo), 500 iterations each: one batched solve (persistent launch
-    per iteration over all blocks, autotuned tiles, graph replay) against the
-    plain per-block solve of the same blocks; results compared bit for bit."""
+    2-voxel halo), 500 iterations each: one batched solve (a persistent
+    launch per two iterations over all blocks, graph replay) against the
+    batched one-iteration kernel with autotuned tiles and against solving
+    the blocks one by one (autotuned tiles, and the library's defaults);
+    results compared bit for bit."""
     import torch
     import paper_2107_14790_amd as tgv
     from paper_2107_14790_amd.autotune import Autotuner
@@ -358,8 +360,20 @@ def bench_city_batch(args):
     log(f"autotune {time.perf_counter() - t0:.1f} s: tile_y {tune['tile_y']}, classes "
         + ", ".join(f"{k}:{v['tile_y']}x{v['tile_z']}" for k, v in tune["classes"].items()))
     params = tgv.Params(iters=iters, storage=storage, tile_y=tune["tile_y"], flags=tgv.FLAG_GRAPH)
+    sched = tgv.SCHED_FUSED2 if args.schedule == "fused2" else tgv.SCHED_FUSED
+    params2 = tgv.Params(iters=iters, storage=storage, schedule=sched, flags=tgv.FLAG_GRAPH)
 
     def batched():
+        # the default: two iterations per persistent launch (or one, with --schedule fused)
+        for st, u0 in zip(states, u0s):
+            st.reset(u0)
+        if sched == tgv.SCHED_FUSED2:
+            ctx.solve_batch(states, hists, params2)
+        else:
+            ctx.solve_batch(states, hists, params, tile_z=tune["tile_z"])
+
+    def batched_one_pass():
+        # one iteration per persistent launch, autotuned tiles
         for st, u0 in zip(states, u0s):
             st.reset(u0)
         ctx.solve_batch(states, hists, params, tile_z=tune["tile_z"])
@@ -370,10 +384,17 @@ def bench_city_batch(args):
             ctx.solve(st.grid, h, None, tgv.Params(iters=iters, storage=storage, tile_y=tune["tile_y"], tile_z=tz),
                       state=st)
 
+    def plain_default():
+        # one by one with the library's defaults (schedule AUTO, tiles and chunk depth chosen per block)
+        for st, u0, h in zip(states, u0s, hists):
+            st.reset(u0)
+            ctx.solve(st.grid, h, None, tgv.Params(iters=iters, storage=storage), state=st)
+
     batched()  # warm (graph capture)
     torch.cuda.synchronize()
     times = {}
-    for name, fn in (("batched", batched), ("plain", plain)):
+    for name, fn in (("batched", batched), ("batched_one_pass", batched_one_pass), ("plain", plain),
+                     ("plain_default", plain_default)):
         ts = []
         for _ in range(max(1, args.steps)):
             torch.cuda.synchronize()
@@ -385,7 +406,12 @@ def bench_city_batch(args):
         log(f"{name}: {[round(x, 3) for x in ts]} s")
         if name == "batched":
             ref = [st.export()["u"] for st in states[:8]]
-    same = all(torch.equal(a, st.export()["u"]) for a, st in zip(ref, states[:8]))
+        if name == "plain_default":
+            same_default = all(torch.equal(a, st.export()["u"]) for a, st in zip(ref, states[:8]))
+        if name == "batched_one_pass":
+            same_one = all(torch.equal(a, st.export()["u"]) for a, st in zip(ref, states[:8]))
+        if name == "plain":
+            same = all(torch.equal(a, st.export()["u"]) for a, st in zip(ref, states[:8]))
     tb, tp = min(times["batched"]), min(times["plain"])
     bpv = fused_bytes_per_voxel(storage)
     out = {
@@ -399,13 +425,18 @@ def bench_city_batch(args):
         "data": "synthetic",
         "config": {"workload": "city_batch", "blocks": len(grids), "edge": "log-uniform 32..128 + 2 halo",
                    "iters": iters, "cameras": len(sc.cams), "image": [W, H], "padded_voxels": padded,
-                   "interior_voxels": interior, "tile_y": tune["tile_y"]},
+                   "interior_voxels": interior, "tile_y": tune["tile_y"], "schedule": args.schedule},
         "batched": {"s": tb, "blocks_per_s": len(grids) / tb, "updates_per_s_interior": interior * iters / tb,
                     "algorithmic_GBs": bpv * padded * iters / tb / 1e9},
         "plain": {"s": tp, "blocks_per_s": len(grids) / tp, "updates_per_s_interior": interior * iters / tp,
                   "algorithmic_GBs": bpv * padded * iters / tp / 1e9},
+        "batched_one_pass_autotuned": {"s": min(times["batched_one_pass"]),
+                                       "updates_per_s_interior": interior * iters / min(times["batched_one_pass"])},
+        "plain_library_defaults": {"s": min(times["plain_default"]),
+                                   "blocks_per_s": len(grids) / min(times["plain_default"]),
+                                   "updates_per_s_interior": interior * iters / min(times["plain_default"])},
         "speedup_batched_vs_plain": tp / tb,
-        "bitwise_same_alone_and_batched": bool(same),
+        "bitwise_same_alone_and_batched": bool(same and same_default and same_one),
         "phases_ms": {"pyramids": pyr_ms, "histograms_all_blocks": hist_ms},
     }
     print(json.dumps(out), flush=True)

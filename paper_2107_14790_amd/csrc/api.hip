@@ -568,10 +568,13 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
             }
             launch_ref(KIND_DUAL, st->storage, b, d, cf, s);
         }
-        // AUTO: two iterations per pass where the block is large, else one
+        // AUTO: two iterations per pass unless the block is small (measured
+        // crossover near 96^3 in float32 and 16-bit storage: 48 MiB per iteration)
         int sched = params->schedule;
-        if (sched == TGV_SCHED_AUTO)
-            sched = (params->tile_y == 0 && stream_stores(st->storage, d)) ? TGV_SCHED_FUSED2 : TGV_SCHED_FUSED;
+        if (sched == TGV_SCHED_AUTO) {
+            const long long per_voxel = st->storage == 0 ? 120 : 72;
+            sched = (params->tile_y == 0 && d.n * per_voxel > (48LL << 20)) ? TGV_SCHED_FUSED2 : TGV_SCHED_FUSED;
+        }
         if (sched == TGV_SCHED_SPLIT) {
             for (int it = 0; it < N; it++) {
                 if (it > 0) launch_ref(KIND_DUAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
@@ -580,7 +583,8 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
             }
         } else {
             int ty = params->tile_y ? params->tile_y : default_tile_y(st->storage, d);
-            int cz = params->tile_z ? params->tile_z : DEFAULT_TILE_Z;
+            int cz = params->tile_z ? params->tile_z
+                                    : choose_tile_z(d, ty, ctx->cus * tiled_blocks_per_cu(st->storage, ty, d));
             int it = 0;
             if (sched == TGV_SCHED_FUSED2 && tiled_fits(d)) {
                 // pairs of fused iterations in one pass; x^{n+1} is never
@@ -595,6 +599,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
                     st->yc ^= 1;
                 }
                 ty = default_tile_y(st->storage, d);
+                if (!params->tile_z) cz = choose_tile_z(d, ty, ctx->cus * tiled_blocks_per_cu(st->storage, ty, d));
             }
             for (; it + 1 < N; it++) {
                 SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
@@ -620,9 +625,16 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
 // ===========================================================================
 // batched solve
 // ===========================================================================
-static int persistent_grid(tgv_ctx *ctx, int storage, int ty, int ntiles) {
+// chunk depth of a block in a batched launch: the launch holds many tiles, so
+// rounds matter little and deep chunks keep the z-halo small
+static int batch_tile_z(const Dims &d, bool two) {
+    if (!two) return DEFAULT_TILE_Z;
+    return d.nz < 32 ? d.nz : 32;
+}
+
+static int persistent_grid(tgv_ctx *ctx, int storage, int ty, int ntiles, bool two) {
     // as many workgroups as can be resident at once (occupancy of the batched kernel)
-    int g = ctx->cus * batch_blocks_per_cu(storage, ty);
+    int g = ctx->cus * (two ? batch2_blocks_per_cu(storage, ty) : batch_blocks_per_cu(storage, ty));
     g = (g + 7) / 8 * 8;
     int cap = (ntiles + 7) / 8 * 8;
     return g < cap ? g : cap;
@@ -648,8 +660,11 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
     hipStream_t s = S(stream);
     Coef cf = make_coef(*params, *bins);
     const int N = params->iters;
-    const int ty = params->tile_y ? params->tile_y : DEFAULT_BATCH_TILE_Y;
-    if (!tiled_shape_ok(ty, 1)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: tile_y %d", ty);
+    // two iterations per launch (FUSED2, or AUTO without a given tile), else one
+    const bool two = params->schedule == TGV_SCHED_FUSED2 || (params->schedule == TGV_SCHED_AUTO && params->tile_y == 0);
+    const int ty = params->tile_y ? params->tile_y : (two ? DEFAULT_TILE2_Y : DEFAULT_BATCH_TILE_Y);
+    if (two ? !tiled2_shape_ok(ty, 1) : !tiled_shape_ok(ty, 1))
+        return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: tile_y %d", ty);
     if (n == 0 || N == 0) {
         if (stats_host)
             for (int i = 0; i < n; i++) {
@@ -677,7 +692,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
         for (int i = 0; i < n; i++) {
             Dims d = make_dims(states[i]->grid);
             if (!tiled_fits(d)) continue;
-            int cz = tile_z_host ? tile_z_host[i] : (params->tile_z ? params->tile_z : DEFAULT_TILE_Z);
+            int cz = tile_z_host ? tile_z_host[i] : (params->tile_z ? params->tile_z : batch_tile_z(d, two));
             tiles += (long long)((d.nx + 63) / 64) * ((d.ny + ty - 1) / ty) * ((d.nz + cz - 1) / cz);
         }
         if (tiles > (1LL << 30)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: too many tiles");
@@ -715,7 +730,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
                 big.push_back(i);
                 continue;
             }
-            int cz = tile_z_host ? tile_z_host[i] : (params->tile_z ? params->tile_z : DEFAULT_TILE_Z);
+            int cz = tile_z_host ? tile_z_host[i] : (params->tile_z ? params->tile_z : batch_tile_z(d, two));
             BatchBlock &bb = ctx->bt_blocks_host[nb];
             for (int k = 0; k < 2; k++) {
                 bb.u[k] = st->u[k];
@@ -743,20 +758,29 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
         HIP_TRY(ctx, hipEventRecord(ctx->bt_evt, s));
     }
     // 3. N-1 fused iterations of all blocks: one persistent launch each
-    const int grid = persistent_grid(ctx, params->storage, ty, nt);
+    const int grid = persistent_grid(ctx, params->storage, ty, nt, two);
     const int F = N - 1;
-    if (nb > 0 && F > 0) {
-        const bool use_graph = (params->flags & TGV_FLAG_GRAPH) && F >= 2;
+    // batched launches: F one-iteration passes, or F/2 two-iteration passes
+    // (plus, for an odd F, one one-iteration pass per block after them)
+    const int LB = two ? F / 2 : F;
+    auto launch_one = [&](int flip, hipStream_t st_) {
+        if (two)
+            launch_batch2(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters, cf,
+                          ty, flip, grid, st_);
+        else
+            launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters, cf,
+                         ty, flip, grid, st_);
+    };
+    if (nb > 0 && LB > 0) {
+        const bool use_graph = (params->flags & TGV_FLAG_GRAPH) && LB >= 2;
         if (!use_graph) {
-            for (int it = 0; it < F; it++)
-                launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters,
-                             cf, ty, it & 1, grid, s);
+            for (int it = 0; it < LB; it++) launch_one(it & 1, s);
         } else {
-            // the graph holds two iterations (parity 0 then 1); it is keyed by
+            // the graph holds two launches (parity 0 then 1); it is keyed by
             // everything its kernel arguments capture
             char key[256];
-            int kl = snprintf(key, sizeof(key), "%d|%d|%d|%d|%d|%p|%p|%p|", params->storage, ty, nt, grid, nb,
-                              (void *)ctx->bt_blocks_dev, (void *)ctx->bt_tiles_dev, (void *)ctx->counters);
+            int kl = snprintf(key, sizeof(key), "%d|%d|%d|%d|%d|%d|%p|%p|%p|", params->storage, (int)two, ty, nt, grid,
+                              nb, (void *)ctx->bt_blocks_dev, (void *)ctx->bt_tiles_dev, (void *)ctx->counters);
             std::string k(key, kl);
             k.append((const char *)&cf, sizeof(cf));
             HIP_TRY(ctx, hipEventRecord(ctx->ev_a, s));
@@ -768,9 +792,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
                 }
                 hipGraph_t g = nullptr;
                 HIP_TRY(ctx, hipStreamBeginCapture(ctx->side, hipStreamCaptureModeThreadLocal));
-                for (int it = 0; it < 2; it++)
-                    launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt,
-                                 ctx->counters, cf, ty, it, grid, ctx->side);
+                for (int it = 0; it < 2; it++) launch_one(it, ctx->side);
                 HIP_TRY(ctx, hipStreamEndCapture(ctx->side, &g));
                 hipError_t e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
@@ -780,14 +802,28 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
                 }
                 ctx->graph_key = k;
             }
-            for (int r = 0; r < F / 2; r++) HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->side));
-            if (F & 1)
-                launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters,
-                             cf, ty, 0, grid, ctx->side);
+            for (int r = 0; r < LB / 2; r++) HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->side));
+            if (LB & 1) launch_one(0, ctx->side);
             HIP_TRY(ctx, hipEventRecord(ctx->ev_b, ctx->side));
             HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->ev_b, 0));
         }
     }
+    // the odd pass left by two-iteration launches: one per block
+    const bool leftover = two && (F & 1);
+    if (leftover) {
+        for (int i = 0; i < n; i++) {
+            tgv_state *st = states[i];
+            Dims d = make_dims(st->grid);
+            if (!tiled_fits(d)) continue;
+            const int xc = st->xc ^ (LB & 1), yc = st->yc ^ (LB & 1);
+            const int ty1 = default_tile_y(st->storage, d);
+            launch_tiled(st->storage, bufs_of(st, xc, yc, hist[i]), d, cf, ty1,
+                         choose_tile_z(d, ty1, ctx->cus * tiled_blocks_per_cu(st->storage, ty1, d)), s);
+        }
+    }
+    // buffer flips of a tiled block (one per launch) and of a block too large
+    // for the tiled kernels (one per iteration)
+    const int tiled_flips = LB + (leftover ? 1 : 0);
     // blocks too large for the batched kernel: their own fused launches
     for (int i : big) {
         tgv_state *st = states[i];
@@ -799,11 +835,12 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             yc ^= 1;
         }
     }
-    // 4. parities after F fused iterations, then the closing primal step
+    // 4. parities after the fused passes, then the closing primal step
     for (int i = 0; i < n; i++) {
         tgv_state *st = states[i];
-        st->xc ^= (F & 1);
-        st->yc ^= (F & 1);
+        const int flips = tiled_fits(make_dims(st->grid)) ? tiled_flips : F;
+        st->xc ^= (flips & 1);
+        st->yc ^= (flips & 1);
         launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist[i]), make_dims(st->grid), cf, s);
         st->xc ^= 1;
         st->fresh = false;

@@ -103,6 +103,13 @@ bool tiled2_shape_ok(int ty, int cz);
 int tiled2_blocks_per_cu(int storage, int ty);
 int choose_tile2_z(const Dims &d, int ty, int slots);
 int batch_blocks_per_cu(int storage, int ty);
+// batched two-iteration pass (tiles 64 x ty, ty in {4, 6, 7}); resets the queue counters first
+int batch2_blocks_per_cu(int storage, int ty);
+void launch_batch2(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
+                   int ty, int flip, int grid, hipStream_t s);
+void launch_reset_counters(int *counters, hipStream_t s);
+int tiled_blocks_per_cu(int storage, int ty, const Dims &d);
+int choose_tile_z(const Dims &d, int ty, int slots);
 void launch_tiled2(int storage, const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s);
 // one fused iteration of every block listed in `tiles` (int4: block, tix | tiy << 16, tiz, 0)
 void launch_batch(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,

@@ -402,6 +402,10 @@ __global__ void k_reset_counters(int *counters) {
     if (threadIdx.x < 8) counters[threadIdx.x] = 0;
 }
 
+void launch_reset_counters(int *counters, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters);
+}
+
 template <int STORE, int TY, int SCP>
 static void launch_tiled_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
     XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
@@ -459,6 +463,52 @@ void launch_batch(int storage, const BatchBlock *blocks, const int4 *tiles, int 
     if (storage == 0) launch_batch_t<0>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
     else if (storage == 1) launch_batch_t<1>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
     else launch_batch_t<2>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
+}
+
+// resident workgroups per CU of the one-block kernel
+template <int STORE, int TY, int SCP>
+static int tiled_per_cu_t() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused_tiled<STORE, TY, SCP>, TX * (TY + 3), 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <int STORE, int SCP>
+static int tiled_per_cu_s(int ty) {
+    return ty == 4 ? tiled_per_cu_t<STORE, 4, SCP>()
+                   : (ty == 12 ? tiled_per_cu_t<STORE, 12, SCP>() : tiled_per_cu_t<STORE, 8, SCP>());
+}
+
+int tiled_blocks_per_cu(int storage, int ty, const Dims &d) {
+    if (stream_stores(storage, d))
+        return storage == 0 ? tiled_per_cu_s<0, STORE_CP_STREAM>(ty)
+                            : (storage == 1 ? tiled_per_cu_s<1, STORE_CP_STREAM>(ty) : tiled_per_cu_s<2, STORE_CP_STREAM>(ty));
+    return storage == 0 ? tiled_per_cu_s<0, 0>(ty) : (storage == 1 ? tiled_per_cu_s<1, 0>(ty) : tiled_per_cu_s<2, 0>(ty));
+}
+
+// Planes per z-chunk of the one-block kernel: the depth up to 32 that
+// minimises rounds of resident workgroups x (cz + 2) plane steps.  A block
+// with enough tiles keeps 32 planes (256^3: 1024 tiles, two full rounds;
+// deeper chunks were slower there, as neighbouring tiles drift further
+// apart); a small block gets short chunks, so that its tiles fill the GPU
+// instead of a few workgroups walking 32 planes each (64^3: 2 planes, 51 us
+// per iteration with 32).
+int choose_tile_z(const Dims &d, int ty, int slots) {
+    const long long per_chunk = (long long)((d.nx + TX - 1) / TX) * ((d.ny + ty - 1) / ty);
+    const int hi = d.nz < 32 ? d.nz : 32;
+    long long best = -1;
+    int best_cz = hi;
+    for (int cz = hi; cz >= 1; cz--) {
+        const long long tiles = per_chunk * ((d.nz + cz - 1) / cz);
+        const long long rounds = (tiles + slots - 1) / slots;
+        const long long cost = rounds * (cz + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_cz = cz;
+        }
+    }
+    return best_cz;
 }
 
 bool tiled_fits(const Dims &d) {

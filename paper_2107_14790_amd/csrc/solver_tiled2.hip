@@ -128,20 +128,17 @@ struct Stage {
 
 }  // namespace
 
+// Two fused iterations on tile (tix, tiy, tiz) of a block: Xc, Yc in, Xn, Yn
+// out.  Every thread of the workgroup must call it (it holds barriers).
 template <int STORE, int TY, int SCP>
-__global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
-    k_fused2_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn, YBuf<STORE> Yn, const uint16_t *__restrict__ hist,
-                   Dims d, Coef cf, int CZ, int ntx, int nty, int ntz) {
+__device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf<STORE> &Xc, const YBuf<STORE> &Yc,
+                                          const XBuf<STORE> &Xn, const YBuf<STORE> &Yn,
+                                          const uint16_t *__restrict__ hist, const Dims &d, const Coef &cf, int CZ,
+                                          int tix, int tiy, int tiz) {
     using L = XLds<TY>;
     constexpr int EX = L::EX, NE = L::NE;
     constexpr int SB = STORE == 0 ? 4 : 2;
-    __shared__ L la, lb;
-
-    const int nb = ntx * nty * ntz;
-    const int per = (nb + 7) / 8;
-    const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (T >= nb) return;
-    const int x0 = (T % ntx) * TX, y0 = ((T / ntx) % nty) * TY, z0 = (T / (ntx * nty)) * CZ;
+    const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * CZ;
     const int zl = min(z0 + CZ, d.nz) - 1;
 
     // ---- the column this thread owns and its roles in both stages
@@ -440,6 +437,53 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
 }
 
 template <int STORE, int TY, int SCP>
+__global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
+    k_fused2_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn, YBuf<STORE> Yn, const uint16_t *__restrict__ hist,
+                   Dims d, Coef cf, int CZ, int ntx, int nty, int ntz) {
+    __shared__ XLds<TY> la, lb;
+    // XCD-aware tile order, as in the one-iteration kernel
+    const int nb = ntx * nty * ntz;
+    const int per = (nb + 7) / 8;
+    const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (T >= nb) return;
+    run_tile2<STORE, TY, SCP>(la, lb, Xc, Yc, Xn, Yn, hist, d, cf, CZ, T % ntx, (T / ntx) % nty, T / (ntx * nty));
+}
+
+// Batched two-iteration pass: every tile of every block advances two
+// iterations per launch.  Workgroups pull tiles from the same per-XCD queue
+// segments as the one-iteration batched kernel; no workgroup waits on
+// another.
+template <int STORE, int TY>
+__global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
+    k_fused2_batch(const BatchBlock *__restrict__ blocks, const int4 *__restrict__ tiles, int ntiles, int *counters,
+                   Coef cf, int flip) {
+    __shared__ XLds<TY> la, lb;
+    __shared__ int s_tile;
+    const int seg_len = (ntiles + 7) / 8;
+    const int home = (int)(blockIdx.x % 8);
+    for (int k = 0; k < 8; k++) {
+        const int seg = (home + k) & 7;
+        const int seg_end = min(seg_len * (seg + 1), ntiles);
+        while (true) {
+            if (threadIdx.x == 0) s_tile = seg * seg_len + atomicAdd(&counters[seg], 1);
+            lds_barrier2();
+            const int ti = s_tile;
+            lds_barrier2();  // everyone has read s_tile before it is rewritten
+            if (ti >= seg_end) break;
+            const int4 tr = tiles[ti];
+            const BatchBlock &bb = blocks[tr.x];
+            const int xc = bb.xc ^ flip, yc = bb.yc ^ flip;
+            XBuf<STORE> Xc{bb.u[xc], (typename Store<STORE>::T *)bb.v[xc]};
+            XBuf<STORE> Xn{bb.u[xc ^ 1], (typename Store<STORE>::T *)bb.v[xc ^ 1]};
+            YBuf<STORE> Yc{(typename Store<STORE>::T *)bb.p[yc], (typename Store<STORE>::T *)bb.q[yc]};
+            YBuf<STORE> Yn{(typename Store<STORE>::T *)bb.p[yc ^ 1], (typename Store<STORE>::T *)bb.q[yc ^ 1]};
+            run_tile2<STORE, TY, 0>(la, lb, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz, tr.y & 0xffff, tr.y >> 16, tr.z);
+            lds_barrier2();  // the tile's LDS reads are done before the next tile writes
+        }
+    }
+}
+
+template <int STORE, int TY, int SCP>
 static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
     XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
     XBuf<STORE> Xo{b.xo_u, (typename Store<STORE>::T *)b.xo_v};
@@ -460,6 +504,42 @@ static void launch2_t(const SolveBufs &b, const Dims &d, const Coef &cf, int ty,
 }
 
 bool tiled2_shape_ok(int ty, int cz) { return (ty == 4 || ty == 6 || ty == 7) && cz >= 1; }
+
+template <int STORE, int TY>
+static int batch2_per_cu_t() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused2_batch<STORE, TY>, TX * (TY + 5), 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int batch2_blocks_per_cu(int storage, int ty) {
+    if (storage == 0) return ty == 4 ? batch2_per_cu_t<0, 4>() : (ty == 6 ? batch2_per_cu_t<0, 6>() : batch2_per_cu_t<0, 7>());
+    if (storage == 1) return ty == 4 ? batch2_per_cu_t<1, 4>() : (ty == 6 ? batch2_per_cu_t<1, 6>() : batch2_per_cu_t<1, 7>());
+    return ty == 4 ? batch2_per_cu_t<2, 4>() : (ty == 6 ? batch2_per_cu_t<2, 6>() : batch2_per_cu_t<2, 7>());
+}
+
+template <int STORE>
+static void launch_batch2_t(const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
+                            int ty, int flip, int grid, hipStream_t s) {
+    if (ty == 4)
+        hipLaunchKernelGGL((k_fused2_batch<STORE, 4>), dim3(grid), dim3(TX * 9), 0, s, blocks, tiles, ntiles, counters,
+                           cf, flip);
+    else if (ty == 6)
+        hipLaunchKernelGGL((k_fused2_batch<STORE, 6>), dim3(grid), dim3(TX * 11), 0, s, blocks, tiles, ntiles,
+                           counters, cf, flip);
+    else
+        hipLaunchKernelGGL((k_fused2_batch<STORE, 7>), dim3(grid), dim3(TX * 12), 0, s, blocks, tiles, ntiles,
+                           counters, cf, flip);
+}
+
+void launch_batch2(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
+                   int ty, int flip, int grid, hipStream_t s) {
+    launch_reset_counters(counters, s);
+    if (storage == 0) launch_batch2_t<0>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
+    else if (storage == 1) launch_batch2_t<1>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
+    else launch_batch2_t<2>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
+}
 
 // resident workgroups per CU of the two-iteration kernel
 template <int STORE, int TY>
@@ -486,10 +566,10 @@ int tiled2_blocks_per_cu(int storage, int ty) {
 // rounds x (cz + 3) is taken (ties: the deeper chunk).  On a 256^3 block with
 // 64 x 7 tiles and 256 slots this picks 52 planes (740 tiles in three nearly
 // full rounds); the model's ratios for 64 and 26 planes (1.22, 1.06) match
-// the measured times (1.20, 1.05).
+// the measured times (1.20, 1.05).  Small blocks get short chunks.
 int choose_tile2_z(const Dims &d, int ty, int slots) {
     const long long per_chunk = (long long)((d.nx + TX - 1) / TX) * ((d.ny + ty - 1) / ty);
-    const int lo = d.nz < 8 ? d.nz : 8;
+    const int lo = 1;
     long long best = -1;
     int best_cz = d.nz;
     for (int cz = d.nz; cz >= lo; cz--) {
