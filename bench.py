@@ -466,7 +466,10 @@ def bench_city_serve(args):
     pyr = ctx.build_pyramids(torch.from_numpy(sc.depth).cuda())
     torch.cuda.synchronize()
     pool = scenes.city_blocks(sc, n_blocks=max(args.arrivals, 64), e_min=32, e_max=192, seed=5)
-    params = tgv.Params(iters=iters, storage=storage, tile_y=4, flags=tgv.FLAG_GRAPH)
+    if args.schedule == "fused2":  # two iterations per persistent launch
+        params = tgv.Params(iters=iters, storage=storage, schedule=tgv.SCHED_FUSED2, flags=tgv.FLAG_GRAPH)
+    else:
+        params = tgv.Params(iters=iters, storage=storage, schedule=tgv.SCHED_FUSED, tile_y=4, flags=tgv.FLAG_GRAPH)
     budget = 200 << 30
 
     def run(rate, count, seed):
@@ -510,7 +513,8 @@ def bench_city_serve(args):
         "dtype": "f32" if storage == 0 else "f32 compute, " + args.storage + " storage",
         "data": "synthetic",
         "config": {"workload": "city_serve", "rate_per_s": args.rate, "arrivals": args.arrivals,
-                   "edge": "log-uniform 32..192 + 2 halo", "iters": iters, "budget_GB": 200, "tick_iters": 50},
+                   "edge": "log-uniform 32..192 + 2 halo", "iters": iters, "budget_GB": 200, "tick_iters": 50,
+                   "schedule": args.schedule},
         "latency_s": {"p50": hot.get("p50_s"), "p99": hot.get("p99_s")},
         "at_rate": hot,
         "measured_capacity_blocks_per_s": cap,

@@ -808,18 +808,15 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->ev_b, 0));
         }
     }
-    // the odd pass left by two-iteration launches: one per block
-    const bool leftover = two && (F & 1);
+    // the odd pass left by two-iteration launches: one batched one-iteration
+    // launch over the same tile table
+    const bool leftover = two && (F & 1) && nb > 0;
     if (leftover) {
-        for (int i = 0; i < n; i++) {
-            tgv_state *st = states[i];
-            Dims d = make_dims(st->grid);
-            if (!tiled_fits(d)) continue;
-            const int xc = st->xc ^ (LB & 1), yc = st->yc ^ (LB & 1);
-            const int ty1 = default_tile_y(st->storage, d);
-            launch_tiled(st->storage, bufs_of(st, xc, yc, hist[i]), d, cf, ty1,
-                         choose_tile_z(d, ty1, ctx->cus * tiled_blocks_per_cu(st->storage, ty1, d)), s);
-        }
+        int g1 = ctx->cus * batch_blocks_per_cu(params->storage, ty);
+        g1 = (g1 + 7) / 8 * 8;
+        const int cap = (nt + 7) / 8 * 8;
+        launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters, cf, ty,
+                     LB & 1, g1 < cap ? g1 : cap, s);
     }
     // buffer flips of a tiled block (one per launch) and of a block too large
     // for the tiled kernels (one per iteration)

@@ -434,6 +434,9 @@ static void launch_batch_t(const BatchBlock *blocks, const int4 *tiles, int ntil
     if (ty == 4)
         hipLaunchKernelGGL((k_fused_batch<STORE, 4>), dim3(grid), dim3(TX * 7), 0, s, blocks, tiles, ntiles, counters,
                            cf, flip);
+    else if (ty == 7)  // the odd pass of a two-iteration batch, on its 64 x 7 tile table
+        hipLaunchKernelGGL((k_fused_batch<STORE, 7>), dim3(grid), dim3(TX * 10), 0, s, blocks, tiles, ntiles,
+                           counters, cf, flip);
     else if (ty == 12)
         hipLaunchKernelGGL((k_fused_batch<STORE, 12>), dim3(grid), dim3(TX * 15), 0, s, blocks, tiles, ntiles,
                            counters, cf, flip);
@@ -451,10 +454,14 @@ static int batch_per_cu_t() {
     return nb > 0 ? nb : 1;
 }
 
+template <int STORE>
+static int batch_per_cu_s(int ty) {
+    return ty == 4 ? batch_per_cu_t<STORE, 4>()
+                   : (ty == 12 ? batch_per_cu_t<STORE, 12>() : (ty == 7 ? batch_per_cu_t<STORE, 7>() : batch_per_cu_t<STORE, 8>()));
+}
+
 int batch_blocks_per_cu(int storage, int ty) {
-    if (storage == 0) return ty == 4 ? batch_per_cu_t<0, 4>() : (ty == 12 ? batch_per_cu_t<0, 12>() : batch_per_cu_t<0, 8>());
-    if (storage == 1) return ty == 4 ? batch_per_cu_t<1, 4>() : (ty == 12 ? batch_per_cu_t<1, 12>() : batch_per_cu_t<1, 8>());
-    return ty == 4 ? batch_per_cu_t<2, 4>() : (ty == 12 ? batch_per_cu_t<2, 12>() : batch_per_cu_t<2, 8>());
+    return storage == 0 ? batch_per_cu_s<0>(ty) : (storage == 1 ? batch_per_cu_s<1>(ty) : batch_per_cu_s<2>(ty));
 }
 
 void launch_batch(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
