@@ -14,7 +14,9 @@
  * Conventions for every call:
  *   - Array pointers are DEVICE pointers unless the name ends in _host.
  *     The caller allocates and frees them; the library never frees caller
- *     memory and keeps no pointer to it after the call returns.
+ *     memory and keeps no pointer to it after the call returns, except
+ *     tgv_state_wrap, whose state uses the caller's memory until it is
+ *     destroyed.
  *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
  *     NULL = the null stream) unless documented as synchronising.
  *   - Voxel layout: index x + nx * (y + ny * z) (x fastest).
@@ -92,7 +94,7 @@ enum { TGV_STORE_F32 = 0, TGV_STORE_F16 = 1, TGV_STORE_BF16 = 2 };
  * pass over memory (temporal blocking: the second iteration consumes the
  * first one's results from registers and LDS; tile_y in {4, 6, 7}, default
  * 64 x 7 tiles with the chunk depth chosen for the device); AUTO runs FUSED2
- * for a block whose iteration moves more than 256 MiB (when tile_y is 0)
+ * for a block whose iteration moves more than 48 MiB (when tile_y is 0)
  * and FUSED otherwise.  All of them produce bit-identical results.  A
  * batched solve always runs its persistent one-iteration kernel, whatever
  * the schedule. */
@@ -101,10 +103,11 @@ enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1, TGV_SCHED_FUSED_REF = 2, TGV_SC
 /* Solver parameters (Eq. 2, Sec. 3.2).  tau, sigma: primal and dual step
  * sizes (> 0); iters >= 0 primal-dual iterations.  tile_y, tile_z: shape of
  * the fused kernel's tiles (64 x tile_y columns, tile_z planes per
- * workgroup); 0 picks the library default: 64 x 8 x 32 for a float32
- * block whose iteration moves more than 256 MiB, else 64 x 4 x 32;
- * 64 x 6 x 64 for FUSED2; 64 x 4 for a batched solve (tile_y in {4, 8, 12};
- * in {4, 6, 7} for FUSED2). */
+ * workgroup); 0 picks the library default: tile_y 8 for a float32 block
+ * whose iteration moves more than 256 MiB, else 4; 7 for FUSED2; 4 for a
+ * batched solve (tile_y in {4, 8, 12}; in {4, 6, 7} for FUSED2); tile_z
+ * from a model of the launch's rounds of resident workgroups (up to 32
+ * planes for FUSED; 32 for a batched solve). */
 typedef struct {
     float alpha0, alpha1, lambda;
     float tau, sigma;
@@ -190,7 +193,8 @@ tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32_t W, int32
  * held in device memory owned by the state. */
 tgv_status tgv_state_create(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, tgv_state **out);
 /* Same, in caller-owned device memory of at least tgv_state_bytes(grid,
- * storage) bytes (256-byte aligned); the state never frees it.  Lets a
+ * storage) bytes (256-byte aligned); the state never frees it, and the
+ * memory must outlive the state.  Lets a
  * caller keep states in its own pool (a serving loop, a caching allocator)
  * without device-synchronising frees. */
 tgv_status tgv_state_wrap(tgv_ctx *ctx, const tgv_grid *grid, int32_t storage, void *mem, int64_t bytes,
