@@ -297,6 +297,14 @@ def bench_block(args):
                    "step": "pyramids + cull + histograms + init + iterations + gap"},
         "roofline": roof,
         "one_pass_kernel": reference,
+        # the iteration rate in one-pass terms: what a one-iteration kernel
+        # would have to stream (120 B per update in float32) to match it
+        "iteration_equivalent": (None if roof is None else dict(
+            updates_per_s=round(nvox / (roof["us_per_iteration"] * 1e-6)),
+            bytes_per_update_one_pass=fused_bytes_per_voxel(storage),
+            GBs=round(fused_bytes_per_voxel(storage) * nvox / (roof["us_per_iteration"] * 1e-6) / 1e9, 1),
+            frac_of_peak=round(fused_bytes_per_voxel(storage) * nvox / (roof["us_per_iteration"] * 1e-6) / 1e9
+                               / HBM_PEAK_GBS, 4))),
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "phases_ms": {"pyramids": pyr_ms, "histograms": hist_ms},
