@@ -170,3 +170,32 @@ def test_batch_with_block_beyond_tiled_offsets_and_table_growth(ctx):
     del xb, yb
     for st in (a, b_small, b_big, solo_s, solo_b):
         st.close()
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+@pytest.mark.parametrize("iters", [2, 9, 16])
+def test_two_iteration_batch_equals_solo(ctx, storage, iters):
+    """The default batched solve (two iterations per persistent launch, an
+    odd leftover pass as one batched one-iteration launch) against each block
+    solved alone with the one-iteration kernel, in every storage precision."""
+    import paper_2107_14790_amd as tgv
+    say("two-iteration batch vs solo", storage, iters)
+    blocks = make_blocks(100 + storage)
+    solo, states, hists = [], [], []
+    for shape, halo, hist, u0 in blocks:
+        g = tgv.grid_c((0, 0, 0), 1.0, shape, halo)
+        h = torch.from_numpy(hist.view(np.int16)).cuda()
+        u = torch.from_numpy(u0).cuda()
+        a = tgv.State(ctx, g, storage)
+        a.reset(u)
+        ctx.solve(g, h, None, tgv.Params(iters=iters, storage=storage, schedule=tgv.SCHED_FUSED), state=a)
+        solo.append(fields(a))
+        b = tgv.State(ctx, g, storage)
+        b.reset(u)
+        states.append(b)
+        hists.append(h)
+    ctx.solve_batch(states, hists, tgv.Params(iters=iters, storage=storage))
+    for i, st in enumerate(states):
+        f = fields(st)
+        for k in f:
+            assert np.array_equal(f[k], solo[i][k]), (i, k)
