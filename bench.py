@@ -106,11 +106,25 @@ def cpu_baseline(scene, bins_centers, iters_sample: int = 150, crop: int = 64, n
     oracle.solve(hcrop, (crop, crop, crop), bins_centers, iters_sample)
     t_solve = time.perf_counter() - t0
     ups = crop ** 3 * iters_sample / t_solve
+    # the same sample with the oracle's per-voxel loops on the host's cores
+    # (bit-identical to the serial run; at most 16 threads, the host share
+    # of one GPU)
+    k = max(1, min(16, os.cpu_count() or 1))
+    with oracle.threads(k):
+        t0 = time.perf_counter()
+        oracle.histograms(scene, pyr, vox=vox)
+        t_hist_k = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.solve(hcrop, (crop, crop, crop), bins_centers, iters_sample)
+        t_solve_k = time.perf_counter() - t0
     return dict(value=ups, unit="voxel-updates/s", cores=1, kind="oracle",
                 sample=f"oracle float64 solve of a {crop}^3 crop of the block (mid-height), {iters_sample} "
                        f"iterations, {t_solve:.1f} s; oracle histograms {pairs_s:.3g} pairs/s on "
                        f"{nvox_hist} random voxels x {len(scene.cams)} cameras; pyramids {t_pyr:.1f} s",
-                hist_pairs_per_s=pairs_s)
+                hist_pairs_per_s=pairs_s,
+                all_cores={"value": crop ** 3 * iters_sample / t_solve_k, "unit": "voxel-updates/s", "cores": k,
+                           "hist_pairs_per_s": nvox_hist * len(scene.cams) / t_hist_k,
+                           "sample": "the same sample, the oracle's per-voxel loops on k threads"})
 
 
 def main():

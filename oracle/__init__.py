@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force: bool = True) -> str:
@@ -75,8 +75,40 @@ def lib():
         L.or_dual_energy.restype = c_double
         L.or_norm_K2.argtypes = [c_int, c_int, c_int, c_int, ctypes.c_uint64]
         L.or_norm_K2.restype = c_double
+        L.or_set_threads.argtypes = [c_int]
+        L.or_set_threads.restype = None
+        L.or_get_threads.argtypes = []
+        L.or_get_threads.restype = c_int
         _lib = L
     return _lib
+
+
+def set_threads(k: int) -> None:
+    """Threads of the oracle's per-voxel loops (histogram votes, the dual
+    and primal sweeps).  1, the default, is the plain serial oracle; any
+    other count gives bit-identical results (each loop writes only its own
+    voxel's entries; sums stay serial)."""
+    lib().or_set_threads(int(k))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
+
+
+class threads:
+    """Context manager: run the oracle on k threads inside the block."""
+
+    def __init__(self, k: int):
+        self.k = k
+
+    def __enter__(self):
+        self.prev = get_threads()
+        set_threads(self.k)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.prev)
+        return False
 
 
 # ----------------------------------------------------------------------------

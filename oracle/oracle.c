@@ -31,11 +31,24 @@
  *   the norm of the symmetric matrix, with the matching inner product.
  * Layout: voxel index x + nx*(y + ny*z); vector fields are component-major
  * (v[c*n + idx]); q components ordered xx, yy, zz, xy, xz, yz.
+ *
+ * Threads: single-threaded unless or_set_threads asks for more.  Only the
+ * per-voxel loops of the histogram vote and of the two sweeps of an
+ * iteration (all of which write one voxel's own entries from inputs no
+ * voxel of the same loop writes) are split over threads, so every result
+ * is bit for bit the same at any thread count; sums stay serial.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
+
+static int g_threads = 1;
+
+/* number of threads of the per-voxel loops (1 = the plain serial oracle) */
+void or_set_threads(int k) { g_threads = k > 0 ? k : 1; }
+int or_get_threads(void) { return g_threads; }
 
 /* ======================================================================
  * Part 1: pyramids and histogram votes (canonical binary32)
@@ -198,6 +211,7 @@ long or_histograms(const float *pyrs, int ncam, const float *R, const float *t, 
     for (int c = 0; c < ncam; c++) off[c + 1] = off[c] + or_pyr_floats(wh[2 * c], wh[2 * c + 1]);
     long count = vox ? nvox : (long)nx * ny * nz;
     long maxtot = 0;
+#pragma omp parallel for schedule(dynamic, 256) num_threads(g_threads) reduction(max : maxtot)
     for (long m = 0; m < count; m++) {
         long idx = vox ? (long)vox[m] : m;
         int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((long)nx * ny));
@@ -259,6 +273,7 @@ void or_apply_K(int nx, int ny, int nz, const double *u, const double *v, double
     long st[3];
     strides(d, st);
     long nn[3] = {d.nx, d.ny, d.nz};
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (long x = 0; x < d.n; x++) {
         long c[3];
         coords(d, x, c);
@@ -286,6 +301,7 @@ void or_apply_KT(int nx, int ny, int nz, const double *p, const double *q, doubl
     long st[3];
     strides(d, st);
     long nn[3] = {d.nx, d.ny, d.nz};
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (long x = 0; x < d.n; x++) {
         long c[3];
         coords(d, x, c);
@@ -421,6 +437,7 @@ void or_solve(int nx, int ny, int nz, int halo, const uint16_t *hist, int nbins,
     for (int it = 0; it < iters; it++) {
         /* dual ascent */
         or_apply_K(nx, ny, nz, ubar, vbar, kp, kq);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
         for (long x = 0; x < n; x++) {
             double *pp[3] = {p, p + n, p + 2 * n};
             for (int c = 0; c < 3; c++) p[c * n + x] += sigma * kp[c * n + x];
@@ -432,6 +449,7 @@ void or_solve(int nx, int ny, int nz, int halo, const uint16_t *hist, int nbins,
         }
         /* primal descent */
         or_apply_KT(nx, ny, nz, p, q, gu, gv);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
         for (long x = 0; x < n; x++) {
             double un;
             if (is_frozen(d, x, halo)) {

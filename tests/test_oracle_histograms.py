@@ -175,6 +175,16 @@ def test_sphere_histograms_invariants():
     np.testing.assert_array_equal(oracle.histograms(sc, pyr, vox=sel)[0], full[sel])
 
 
+def test_threaded_histograms_equal_serial():
+    sc = scenes.sphere_scene(n=20)
+    pyr = oracle.pyramids(sc.depth)
+    ref, mx = oracle.histograms(sc, pyr)
+    with oracle.threads(4):
+        got, mx4 = oracle.histograms(sc, pyr)
+    np.testing.assert_array_equal(got, ref)
+    assert mx4 == mx
+
+
 def test_sphere_noise_free_geometry():
     sc = scenes.sphere_scene(n=64, sigma=0.0, outlier_frac=0.0)
     hist, _ = oracle.histograms(sc)

@@ -175,6 +175,24 @@ def test_frozen_halo_and_bitwise_resume():
     assert np.any(a.u[~frozen] != u0[~frozen])
 
 
+@pytest.mark.parametrize("tvl1", [False, True])
+def test_threaded_oracle_is_bitwise_the_serial_one(tvl1):
+    """The per-voxel sweeps split over threads give the serial iterates bit
+    for bit (each voxel's update reads only the previous sweep's arrays)."""
+    rng = np.random.default_rng(17)
+    shape = (23, 17, 11)
+    hist = rand_hist(shape, rng, fully=False)
+    u0 = np.where(rng.random(int(np.prod(shape))) < 0.5, rng.uniform(-1, 1, int(np.prod(shape))), 0.0)
+    ref = oracle.solve(hist, shape, C7, 40, halo=1, u0=u0, tvl1=tvl1)
+    for k in (2, 5):
+        with oracle.threads(k):
+            assert oracle.get_threads() == k
+            got = oracle.solve(hist, shape, C7, 40, halo=1, u0=u0, tvl1=tvl1)
+        assert oracle.get_threads() == 1
+        for f in ("u", "v", "p", "q", "ubar", "vbar"):
+            assert np.array_equal(getattr(ref, f).view(np.uint64), getattr(got, f).view(np.uint64)), (k, f)
+
+
 # ---------------------------------------------------------------------------
 # exact minimum energy in 1-D (linear program)
 # ---------------------------------------------------------------------------
