@@ -22,7 +22,12 @@
  *   - Voxel layout: index x + nx * (y + ny * z) (x fastest).
  *   - Errors are returned as tgv_status; no exception crosses the ABI.
  *     tgv_last_error(ctx) gives a message for the last failing call.
- *   - One context per host thread; a context is not re-entrant.
+ *   - One context per host thread; a context is not re-entrant.  Calls of
+ *     one context may use different streams: work that reuses a buffer the
+ *     context owns (the camera table of tgv_build_histograms, the block and
+ *     tile tables of tgv_solve_batch, the state of a tgv_solve without one)
+ *     waits on the device for the previous call's use of it.  Caller-owned
+ *     arrays and states used on several streams are ordered by the caller.
  *   - Depth maps hold the camera-frame z of the surface seen through each
  *     pixel; values that are not finite or <= 0 mean "no sample".
  *   - Camera model: Xc = R X + t (R row-major); pixel column i covers

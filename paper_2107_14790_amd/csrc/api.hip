@@ -159,7 +159,10 @@ extern "C" tgv_status tgv_create(int device, tgv_ctx **out) {
     c->ext_total_host = nullptr;
     if (hipHostMalloc((void **)&c->ext_total_host, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->cams_evt, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->cams_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->own_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->bt_evt, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->bt_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
@@ -184,7 +187,10 @@ extern "C" void tgv_destroy(tgv_ctx *c) {
     (void)hipFree(c->eout_dev);
     (void)hipHostFree(c->eout_host);
     (void)hipEventDestroy(c->cams_evt);
+    (void)hipEventDestroy(c->cams_done);
+    (void)hipEventDestroy(c->own_done);
     (void)hipEventDestroy(c->bt_evt);
+    (void)hipEventDestroy(c->bt_done);
     (void)hipEventDestroy(c->ev_a);
     (void)hipEventDestroy(c->ev_b);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -309,6 +315,7 @@ extern "C" tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32
     HIP_TRY(ctx, hipEventSynchronize(ctx->cams_evt));
     if (nk > ctx->cams_cap) {
         int cap = std::max(nk, 64);
+        HIP_TRY(ctx, hipEventSynchronize(ctx->cams_done));  // no kernel reads the old table any more
         (void)hipFree(ctx->cams_dev);
         (void)hipHostFree(ctx->cams_host);
         ctx->cams_dev = nullptr;
@@ -331,15 +338,20 @@ extern "C" tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32
         d.pyr = keep[k];
         d.pad[0] = d.pad[1] = 0;
     }
+    PyrGeom g = pyr_geom(W, H);
+    if (g.L > 24) return fail(ctx, TGV_E_INVAL, "image too large");
     if (nk > 0) {
+        // the previous call's kernel (perhaps on another stream) is done with the table
+        HIP_TRY(ctx, hipStreamWaitEvent(S(stream), ctx->cams_done, 0));
         HIP_TRY(ctx, hipMemcpyAsync(ctx->cams_dev, ctx->cams_host, sizeof(CamDev) * nk, hipMemcpyHostToDevice,
                                     S(stream)));
         HIP_TRY(ctx, hipEventRecord(ctx->cams_evt, S(stream)));
     }
-    PyrGeom g = pyr_geom(W, H);
-    if (g.L > 24) return fail(ctx, TGV_E_INVAL, "image too large");
     launch_histograms(pyr, g, ctx->cams_dev, nk, *grid, *bins, hist, S(stream));
-    return check_launch(ctx, "histograms");
+    tgv_status r = check_launch(ctx, "histograms");
+    if (r != TGV_OK) return r;
+    HIP_TRY(ctx, hipEventRecord(ctx->cams_done, S(stream)));
+    return TGV_OK;
 }
 
 // ===========================================================================
@@ -542,7 +554,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
             return fail(ctx, TGV_E_INVAL, "tgv_solve: state does not match grid/storage");
     } else {
         if (ctx->own && (!same_grid(ctx->own->grid, *grid) || ctx->own->storage != params->storage)) {
-            HIP_TRY(ctx, hipStreamSynchronize(s));
+            HIP_TRY(ctx, hipEventSynchronize(ctx->own_done));  // the last solve on it has finished
             tgv_state_destroy(ctx->own);
             ctx->own = nullptr;
         }
@@ -552,6 +564,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
         }
         st = ctx->own;
         st->grid = *grid;
+        HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->own_done, 0));  // a solve on another stream may still use it
         tgv_status r = tgv_state_reset(ctx, st, u_io, stream);
         if (r != TGV_OK) return r;
     }
@@ -617,6 +630,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
         if (r != TGV_OK) return r;
     }
     if (u_io) HIP_TRY(ctx, hipMemcpyAsync(u_io, st->u[st->xc], 4 * st->n, hipMemcpyDeviceToDevice, s));
+    if (!state) HIP_TRY(ctx, hipEventRecord(ctx->own_done, s));
     if (stats_host) return run_energy(ctx, st, hist, bins, params, stats_host, s);
     return TGV_OK;
 }
@@ -697,6 +711,8 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
         }
         if (tiles > (1LL << 30)) return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: too many tiles");
         // a captured graph holds the table addresses: drop it before a table moves
+        if (n > ctx->bt_blocks_cap || tiles > ctx->bt_tiles_cap)
+            HIP_TRY(ctx, hipEventSynchronize(ctx->bt_done));  // no launch reads the old tables any more
         if ((n > ctx->bt_blocks_cap || tiles > ctx->bt_tiles_cap) && ctx->graph_exec) {
             HIP_TRY(ctx, hipStreamSynchronize(ctx->side));
             (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -752,6 +768,8 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
         }
     }
     if (nb > 0) {
+        // the previous batched solve (perhaps on another stream) is done with the tables and counters
+        HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->bt_done, 0));
         HIP_TRY(ctx, hipMemcpyAsync(ctx->bt_blocks_dev, ctx->bt_blocks_host, sizeof(BatchBlock) * nb,
                                     hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipMemcpyAsync(ctx->bt_tiles_dev, ctx->bt_tiles_host, sizeof(int4) * nt, hipMemcpyHostToDevice, s));
@@ -787,6 +805,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             HIP_TRY(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_a, 0));
             if (!ctx->graph_exec || ctx->graph_key != k) {
                 if (ctx->graph_exec) {
+                    HIP_TRY(ctx, hipStreamSynchronize(ctx->side));  // no replay of the old graph in flight
                     (void)hipGraphExecDestroy(ctx->graph_exec);
                     ctx->graph_exec = nullptr;
                 }
@@ -818,6 +837,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
         launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters, cf, ty,
                      LB & 1, g1 < cap ? g1 : cap, s);
     }
+    if (nb > 0) HIP_TRY(ctx, hipEventRecord(ctx->bt_done, s));
     // buffer flips of a tiled block (one per launch) and of a block too large
     // for the tiled kernels (one per iteration)
     const int tiled_flips = LB + (leftover ? 1 : 0);

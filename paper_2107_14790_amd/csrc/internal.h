@@ -140,7 +140,8 @@ struct tgv_ctx {
     tgv::CamDev *cams_host;
     tgv::CamDev *cams_dev;
     int cams_cap;
-    hipEvent_t cams_evt;
+    hipEvent_t cams_evt;   // after the upload of the staging buffer
+    hipEvent_t cams_done;  // after the last kernel that read cams_dev
     // energy reduction scratch
     double *partials;
     int partials_cap;
@@ -148,11 +149,13 @@ struct tgv_ctx {
     tgv::EnergyOut *eout_host;
     // state used by tgv_solve when the caller passes none
     tgv_state *own;
+    hipEvent_t own_done;  // after the last solve that used it
     // batched solves: block and tile tables, queue counters, captured graph
     tgv::BatchBlock *bt_blocks_dev, *bt_blocks_host;
     int4 *bt_tiles_dev, *bt_tiles_host;
     int bt_blocks_cap, bt_tiles_cap;
-    hipEvent_t bt_evt;
+    hipEvent_t bt_evt;   // after the upload of the staging tables
+    hipEvent_t bt_done;  // after the last launch that read the tables and counters
     int *counters;
     hipGraphExec_t graph_exec;
     std::string graph_key;
