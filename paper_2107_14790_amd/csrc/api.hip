@@ -8,7 +8,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "internal.h"
+#include "context.h"
 
 using namespace tgv;
 
