@@ -146,6 +146,9 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     // TY+2: ring-2 row below; TY+3: ring-2 row above; TY+4: the ring
     // columns, the rows' end columns and the two outer corners
     const int w = threadIdx.x / TX, lane = threadIdx.x & (TX - 1);
+    // the tile's rows run both stages and set the length of every phase
+    // between barriers: their waves issue first (256^3: 1 % faster)
+    if (w < TY) __builtin_amdgcn_s_setprio(2);
     int px = -3, py = -3;
     // kind: 0 core, 1 ring-1, 2 ring-2 needing u+, 3 ring-2 needing v+, 4 ring-2 corner, -1 none
     int kind = -1;
