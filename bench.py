@@ -7,8 +7,10 @@ the unit cube fusing 64 nadir 1024x1024 depth maps of a seeded fBm terrain
 (Hurst 0.8, amplitude 0.2), depth noise 0.3 voxel, 1 % outliers, 7 bins,
 alpha1 = 1, alpha0 = 2, lambda = 1, tau = sigma = 1/sqrt(12), 1000 iterations.
 
-The iterations run two per pass over HBM (schedule FUSED2, the fastest on
-a block this size; `--schedule fused` runs one tiled pass per iteration).
+The schedule is the library's default (`--schedule auto`): on a block this
+size the iterations run two per pass over HBM (FUSED2, the fastest here);
+on the 32^3 sphere block, one tiled pass per iteration.  `--schedule fused`
+or `fused2` forces one.
 
 Prints one JSON line (rank 0) with throughput in voxel-updates/s, the
 roofline of the dominant kernel (the two-iteration pass: one pass's
@@ -137,8 +139,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--schedule", default="fused2", choices=["fused", "fused2"],
-                    help="fused2 (default): two iterations per pass over HBM; fused: one tiled pass per iteration")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "fused", "fused2"],
+                    help="auto (the library's default): two fused iterations per pass for a block whose iteration "
+                         "moves more than 48 MiB and for batches, one per pass otherwise")
     ap.add_argument("--blocks", type=int, default=512)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--arrivals", type=int, default=300)
@@ -151,6 +154,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload in ("city_batch", "city_serve", "city_precision") and args.schedule == "auto":
+        args.schedule = "fused2"  # the library's choice for batches and for the 384^3 block
     if args.workload == "city_batch":
         return bench_city_batch(args)
     if args.workload == "city_serve":
@@ -187,9 +192,12 @@ def bench_block(args):
     ctx = tgv.Context(0)
     g = tgv.grid_from(sc.grid)
     bins = tgv.Bins()
+    nvox = g.nx * g.ny * g.nz
+    if args.schedule == "auto":
+        # the library's default for a block with no tile given
+        args.schedule = "fused2" if nvox * fused_bytes_per_voxel(storage) > (48 << 20) else "fused"
     sched = tgv.SCHED_FUSED2 if args.schedule == "fused2" else tgv.SCHED_FUSED
     params = tgv.Params(iters=args.iters, storage=storage, schedule=sched)
-    nvox = g.nx * g.ny * g.nz
     pyr = torch.empty((len(sc.cams), ctx.pyramid_floats(W, H)), dtype=torch.float32, device=dev)
     hist = torch.empty((nvox, 8), dtype=torch.int16, device=dev)
     u = torch.empty(nvox, dtype=torch.float32, device=dev)
