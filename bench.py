@@ -276,13 +276,36 @@ def bench_block(args):
                     bytes_per_voxel=bpv, voxels_per_launch=nvox, iterations_per_launch=per_launch,
                     avg_launch_ms=round(k_ms, 5), us_per_iteration=round(1e3 * k_ms / per_launch, 2))
 
+    def copy_ceiling():
+        """HBM rate of a plain device copy on this GPU (1 GiB read + 1 GiB
+        written, torch's copy kernel, median of 5), the practical ceiling of
+        a single streaming pass."""
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        ms = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            b.copy_(a)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        del a, b
+        t = float(np.median(ms))
+        return dict(GBs=round(2 * (1 << 30) / (t * 1e-3) / 1e9, 1), bytes=2 * (1 << 30), ms=round(t, 4),
+                    kernel="device copy of 1 GiB (read + write), median of 5")
+
     roof = None
     reference = None
+    copy = None
     if not args.kernel_only:
         roof = kernel_roofline(args.schedule)
         if args.schedule == "fused2":
             # the one-iteration kernel on the same block, for comparison
             reference = kernel_roofline("fused")
+        copy = copy_ceiling()
+        log(f"plain copy: {copy['GBs']:.0f} GB/s")
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -327,6 +350,7 @@ def bench_block(args):
             GBs=round(fused_bytes_per_voxel(storage) * nvox / (roof["us_per_iteration"] * 1e-6) / 1e9, 1),
             frac_of_peak=round(fused_bytes_per_voxel(storage) * nvox / (roof["us_per_iteration"] * 1e-6) / 1e9
                                / HBM_PEAK_GBS, 4))),
+        "copy_ceiling": copy,
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "phases_ms": {"pyramids": pyr_ms, "histograms": hist_ms},
