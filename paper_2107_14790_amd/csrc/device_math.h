@@ -27,11 +27,21 @@ struct Store<0> {
     static __device__ __forceinline__ void st(T *p, float v) { *p = v; }
 };
 
+// float32 -> half, rounded once from the float32 value: the optimisation
+// barrier keeps the compiler from folding a fused multiply-add that
+// produced v into a mixed-precision instruction that rounds straight to
+// half (one rounding instead of two), which some kernels would get and
+// others not
+__device__ __forceinline__ __half to_half(float v) {
+    asm volatile("" : "+v"(v));
+    return __float2half_rn(v);
+}
+
 template <>
 struct Store<1> {
     using T = __half;
     static __device__ __forceinline__ float ld(const T *p) { return __half2float(*p); }
-    static __device__ __forceinline__ void st(T *p, float v) { *p = __float2half_rn(v); }
+    static __device__ __forceinline__ void st(T *p, float v) { *p = to_half(v); }
 };
 
 template <>
@@ -64,6 +74,12 @@ __device__ __forceinline__ bool is_frozen(const Dims &d, int x, int y, int z) {
     return h > 0 && (x < h || y < h || z < h || x >= d.nx - h || y >= d.ny - h || z >= d.nz - h);
 }
 
+// a * b + c with one rounding.  The solver's products that feed a sum are
+// fused explicitly (the library is built without automatic contraction,
+// which the histogram rule needs); every solver kernel calls these same
+// functions, so all schedules agree bit for bit.
+__device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Solver constants (float32, as passed through the ABI)
 struct Coef {
     float alpha0, alpha1, tau, sigma, taulam, taulam2;  // taulam = tau lambda, taulam2 = 2 tau lambda
@@ -90,20 +106,20 @@ __device__ __forceinline__ float prox_hist(float ut, const uint32_t hw[4], const
     }
     float W = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));  // exact: integers
     // g_k = ut - tau lambda (2 S_k - W), walked down from g_0 = ut + tau lambda W
-    float g = ut + cf.taulam * W;
+    float g = madd(cf.taulam, W, ut);
     float best = fminf(g, cf.c[0]);
 #pragma unroll
     for (int k = 1; k < 8; k++) {
-        g = g - cf.taulam2 * h[k - 1];
+        g = madd(-cf.taulam2, h[k - 1], g);
         best = fmaxf(best, fminf(g, cf.c[k]));
     }
-    return fmaxf(best, ut - cf.taulam * W);
+    return fmaxf(best, madd(-cf.taulam, W, ut));
 }
 
 // projection onto {|y| <= alpha}: y / max(1, |y| / alpha), as y * alpha / |y|
 // when |y| > alpha (one reciprocal square root); alpha = 0 gives 0
 __device__ __forceinline__ void project3(float &a, float &b, float &c, float alpha) {
-    float n2 = a * a + b * b + c * c;
+    float n2 = madd(c, c, madd(b, b, a * a));
     if (n2 > alpha * alpha) {
         float f = alpha * __builtin_amdgcn_rsqf(n2);
         a = a * f;
@@ -115,9 +131,9 @@ __device__ __forceinline__ void project3(float &a, float &b, float &c, float alp
 // q is a symmetric 3x3 tensor (xx, yy, zz, xy, xz, yz); its norm counts the
 // off-diagonal entries twice (Frobenius norm of the matrix)
 __device__ __forceinline__ void project6(float q[6], float alpha) {
-    float d = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-    float o = q[3] * q[3] + q[4] * q[4] + q[5] * q[5];
-    float n2 = d + 2.0f * o;
+    float d = madd(q[2], q[2], madd(q[1], q[1], q[0] * q[0]));
+    float o = madd(q[5], q[5], madd(q[4], q[4], q[3] * q[3]));
+    float n2 = madd(2.0f, o, d);
     if (n2 > alpha * alpha) {
         float f = alpha * __builtin_amdgcn_rsqf(n2);
 #pragma unroll
@@ -147,7 +163,7 @@ __device__ __forceinline__ float primal_u(float u, const float p[3], const float
         if (mlo[i]) divp = divp - pm[i];
     }
     if (frozen) return u;
-    return prox_hist(u + cf.tau * divp, hw, cf);
+    return prox_hist(madd(cf.tau, divp, u), hw, cf);
 }
 
 // qn[i][j] = q_ij(y + e_j) (0 if y_j == n_j - 1); q = q(y)
@@ -167,7 +183,7 @@ __device__ __forceinline__ void primal_v(float vout[3], const float v[3], const 
             if (mhi[j]) w = w + qn[i][j];
             if (mlo[j]) w = w - q[qslot(i, j)];
         }
-        vout[i] = v[i] + cf.tau * w;
+        vout[i] = madd(cf.tau, w, v[i]);
     }
 }
 
@@ -185,9 +201,9 @@ __device__ __forceinline__ void dual_pq(float p[3], float q[6], float ub, const 
     float g[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) g[i] = mhi[i] ? ((ub_hi[i] - ub) - vb[i]) : 0.0f;
-    float a = p[0] + cf.sigma * g[0];
-    float b = p[1] + cf.sigma * g[1];
-    float c = p[2] + cf.sigma * g[2];
+    float a = madd(cf.sigma, g[0], p[0]);
+    float b = madd(cf.sigma, g[1], p[1]);
+    float c = madd(cf.sigma, g[2], p[2]);
     project3(a, b, c, cf.alpha1);
     p[0] = a;
     p[1] = b;
@@ -206,7 +222,7 @@ __device__ __forceinline__ void dual_pq(float p[3], float q[6], float ub, const 
     e[4] = 0.5f * (dm[0][2] + dm[2][0]);
     e[5] = 0.5f * (dm[1][2] + dm[2][1]);
 #pragma unroll
-    for (int k = 0; k < 6; k++) q[k] = q[k] + cf.sigma * e[k];
+    for (int k = 0; k < 6; k++) q[k] = madd(cf.sigma, e[k], q[k]);
     project6(q, cf.alpha0);
 }
 

@@ -66,7 +66,7 @@ struct Io<1> {
     }
     template <int CP = 0>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int voff, int soff, float v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, CP);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(to_half(v)), r, voff, soff, CP);
     }
 };
 
