@@ -33,7 +33,7 @@ struct Store<0> {
 // half (one rounding instead of two), which some kernels would get and
 // others not
 __device__ __forceinline__ __half to_half(float v) {
-    asm volatile("" : "+v"(v));
+    asm("" : "+v"(v));
     return __float2half_rn(v);
 }
 
