@@ -135,7 +135,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="terrain256",
-                    choices=["terrain256", "sphere32", "city_batch", "city_serve", "city_precision"])
+                    choices=["terrain256", "sphere32", "city_batch", "city_serve", "city_precision", "next"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
@@ -156,6 +156,8 @@ def main():
         sys.exit(2)
     if args.workload in ("city_batch", "city_serve", "city_precision") and args.schedule == "auto":
         args.schedule = "fused2"  # the library's choice for batches and for the 384^3 block
+    if args.workload == "next":
+        return bench_next(args)
     if args.workload == "city_batch":
         return bench_city_batch(args)
     if args.workload == "city_serve":
@@ -693,6 +695,126 @@ def bench_city_precision(args):
         "vs_float64_oracle_64cube": vs64,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_next(args):
+    """The rows that widen the core path, measured on the benchmark's 256^3
+    terrain block (64 nadir 1024^2 depth maps): coarse-to-fine (3 levels x
+    200 iterations) beside the plain 1000-iteration solve; the TV-L1 model
+    (Eq. 1) for 1000 iterations; the histogram build with four terrestrial
+    360-degree scans (six 1024^2 faces each, vote 5) added to the stereo
+    maps; and the zero-level extraction from the solved block."""
+    import math
+    import torch
+    import paper_2107_14790_amd as tgv
+    import scenes
+
+    n = args.n
+    iters = args.iters or 1000
+    t0 = time.perf_counter()
+    sc = scenes.terrain_scene(n=n, n_side=8, W=1024, H=1024, f=1536.0, device="cuda")
+    sd, scams = scenes.terrain_scans(n=n, device="cuda")
+    log(f"terrain {n}^3 with {len(sc.cams)} stereo maps and {len(scams)} scan faces in {time.perf_counter() - t0:.1f} s")
+    ctx = tgv.Context(0)
+    H, W = sc.depth.shape[1:]
+    g = tgv.grid_from(sc.grid)
+    nvox = n ** 3
+    s = torch.cuda.current_stream()
+    pyr = ctx.build_pyramids(torch.from_numpy(sc.depth).cuda())
+    hist = ctx.build_histograms(pyr, W, H, sc.cams, g)
+    torch.cuda.synchronize()
+
+    def timed(fn, reps=3):
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    def per_iteration_ms(params_of):
+        # median difference of 400- and 200-iteration solves
+        u = torch.zeros(nvox, device="cuda")
+        t = {}
+        for its in (200, 400) * 3:
+            u.zero_()
+            t.setdefault(its, []).append(timed(lambda: ctx.solve(g, hist, u, params_of(its)), reps=1))
+        return (float(np.median(t[400])) - float(np.median(t[200]))) / 200
+
+    out = {}
+    # plain solve, the reference of the rows below
+    u = torch.zeros(nvox, device="cuda")
+    ms_plain = timed(lambda: (u.zero_(), ctx.solve(g, hist, u, tgv.Params(iters=iters))))
+    u_plain = u.clone()
+    # 1. coarse-to-fine
+    levels, it_lvl = 3, 200
+    c2f_updates = sum(math.ceil(n / 2 ** k) ** 3 for k in range(levels)) * it_lvl
+    ms_c2f = timed(lambda: ctx.solve_coarse_to_fine(pyr, W, H, sc.cams, g, levels, tgv.Params(iters=it_lvl)))
+    out["coarse_to_fine"] = {"levels": levels, "iters_per_level": it_lvl, "ms": ms_c2f,
+                             "updates_per_s": c2f_updates / (ms_c2f * 1e-3),
+                             "plain_solve_ms": ms_plain, "plain_iters": iters,
+                             "note": "histograms of every level built inside the call; includes them"}
+    log(f"coarse-to-fine {levels} x {it_lvl}: {ms_c2f:.1f} ms (plain {iters}: {ms_plain:.1f} ms)")
+    # 2. TV-L1: whole solve and the dominant kernel's per-iteration time
+    ms_tv = timed(lambda: (u.zero_(), ctx.solve(g, hist, u, tgv.Params(iters=iters, flags=tgv.FLAG_TVL1))))
+    it_tv = per_iteration_ms(lambda its: tgv.Params(iters=its, flags=tgv.FLAG_TVL1))
+    it_tgv = per_iteration_ms(lambda its: tgv.Params(iters=its))
+    # TV-L1 needs u, p and the histogram: read 4 + 12 + 16, write 4 + 12 = 48 B per update; the
+    # kernels move the TGV state (120 B), with v and q held at zero
+    out["tvl1"] = {"iters": iters, "ms": ms_tv, "updates_per_s": nvox * iters / (ms_tv * 1e-3),
+                   "us_per_iteration": 1e3 * it_tv, "tgv_us_per_iteration": 1e3 * it_tgv,
+                   "roofline": {"bound": "hbm", "achieved": round(48 * nvox / (it_tv * 1e-3) / 1e9, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(48 * nvox / (it_tv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "bytes_per_update": 48, "bytes_moved_per_update": 120}}
+    log(f"TV-L1 {iters}: {ms_tv:.1f} ms, {1e3 * it_tv:.1f} us per iteration (TGV {1e3 * it_tgv:.1f})")
+    # 3. vote 5: stereo maps plus terrestrial scans
+    depth_all = torch.from_numpy(np.concatenate([sc.depth, sd])).cuda()
+    cams_all = scenes.concat_cameras(sc.cams, scams)
+    pyr_all = ctx.build_pyramids(depth_all)
+    del depth_all
+    h_all = ctx.build_histograms(pyr_all, W, H, cams_all, g)
+    ms_h = timed(lambda: ctx.build_histograms(pyr_all, W, H, cams_all, g, out=h_all), reps=5)
+    ms_h0 = timed(lambda: ctx.build_histograms(pyr, W, H, sc.cams, g, out=hist), reps=5)
+    pairs = nvox * len(cams_all)
+    out["vote5_scans"] = {"stereo_maps": len(sc.cams), "scan_faces": len(scams), "ms": ms_h,
+                          "pairs_per_s": pairs / (ms_h * 1e-3), "stereo_only_ms": ms_h0,
+                          "frac_of_valu_ceiling": round(pairs / (ms_h * 1e-3) / (3.93e13 / 60), 3),
+                          "max_count": int(h_all.view(torch.int16).to(torch.int32).max().item())}
+    del pyr_all
+    log(f"histograms with scans: {ms_h:.2f} ms for {len(cams_all)} maps (stereo only {ms_h0:.2f} ms)")
+    # 4. zero level of the solved block: one call into a preallocated
+    # output (count, offsets, write; the call synchronises)
+    cnt = ctx.extract_crossings(g, u_plain).shape[0]
+    pts = torch.empty((cnt, 4), dtype=torch.float32, device="cuda")
+    ms_x = timed(lambda: ctx.extract_crossings(g, u_plain, out=pts), reps=5)
+    ms_x2 = timed(lambda: ctx.extract_crossings(g, u_plain), reps=5)
+    # two passes over u (count, write) plus 16 B per point
+    xbytes = 2 * 4 * nvox + 16 * cnt
+    out["zero_level"] = {"points": cnt, "ms": ms_x, "voxels_per_s": nvox / (ms_x * 1e-3),
+                         "ms_count_then_write": ms_x2,
+                         "note": "one call into a preallocated output, including its host synchronisation",
+                         "roofline": {"bound": "hbm", "achieved": round(xbytes / (ms_x * 1e-3) / 1e9, 1),
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": round(xbytes / (ms_x * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                      "bytes": xbytes}}
+    log(f"zero level: {cnt} points in {ms_x:.2f} ms")
+    res = {
+        "metric": METRIC,
+        "value": nvox * iters / (ms_tv * 1e-3),
+        "unit": "voxel-updates/s",
+        "n_gpus": 1, "steps": 3, "warmup": 1,
+        "ms_per_step": ms_tv,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "next", "grid": [n, n, n], "cameras": len(sc.cams), "image": [W, H],
+                   "iters": iters, "value_is": "TV-L1 updates/s"},
+    }
+    res.update(out)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

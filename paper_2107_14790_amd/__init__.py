@@ -382,10 +382,21 @@ class Context:
                                                       _stream(stream)))
         return out
 
-    def extract_crossings(self, grid, u: torch.Tensor, stream=None) -> torch.Tensor:
-        """Zero-level points of u as a float32 tensor [count, 4] (X, Y, Z, axis)."""
+    def extract_crossings(self, grid, u: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """Zero-level points of u as a float32 tensor [count, 4] (X, Y, Z, axis).
+        With `out` ([capacity, 4] float32) one call fills it and returns its
+        first count rows (a ValueError if the points do not fit); without, a
+        counting call sizes the output first."""
         g = grid_from(grid)
         cnt = ctypes.c_int64()
+        if out is not None:
+            if out.dtype != torch.float32 or out.dim() != 2 or out.shape[1] != 4:
+                raise ValueError("out must be a float32 tensor [capacity, 4]")
+            self._check(self.lib.tgv_extract_crossings(self.h, ctypes.byref(g), _ptr(u), _ptr(out), out.shape[0],
+                                                       ctypes.byref(cnt), _stream(stream)))
+            if cnt.value > out.shape[0]:
+                raise ValueError(f"{cnt.value} points do not fit in {out.shape[0]} rows")
+            return out[:cnt.value]
         self._check(self.lib.tgv_extract_crossings(self.h, ctypes.byref(g), _ptr(u), None, 0, ctypes.byref(cnt),
                                                    _stream(stream)))
         out = torch.empty((max(cnt.value, 1), 4), dtype=torch.float32, device=u.device)

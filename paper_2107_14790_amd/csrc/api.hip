@@ -886,8 +886,8 @@ extern "C" tgv_status tgv_extract_crossings(tgv_ctx *ctx, const tgv_grid *grid, 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = S(stream);
     Dims d = make_dims(*grid);
-    long long nb = extract_blocks(d);
-    long long need = align256(4 * nb) + 8 * (nb + 1);
+    long long nb = extract_blocks(d), nr = extract_runs(d);
+    long long need = align256(4 * nb) + align256(8 * (nb + 1)) + 8 * nr;
     if (need > ctx->ext_cap) {
         HIP_TRY(ctx, hipStreamSynchronize(s));
         (void)hipFree(ctx->ext_scratch);
@@ -898,7 +898,8 @@ extern "C" tgv_status tgv_extract_crossings(tgv_ctx *ctx, const tgv_grid *grid, 
     }
     unsigned *counts = (unsigned *)ctx->ext_scratch;
     unsigned long long *offsets = (unsigned long long *)((char *)ctx->ext_scratch + align256(4 * nb));
-    launch_extract(u, d, *grid, counts, offsets, (float4 *)points, max_points, s);
+    unsigned long long *runs = (unsigned long long *)((char *)offsets + align256(8 * (nb + 1)));
+    launch_extract(u, d, *grid, counts, offsets, runs, (float4 *)points, max_points, s);
     tgv_status r = check_launch(ctx, "extract crossings");
     if (r != TGV_OK) return r;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->ext_total_host, offsets + nb, sizeof(unsigned long long), hipMemcpyDeviceToHost,

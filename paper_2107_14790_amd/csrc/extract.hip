@@ -5,13 +5,15 @@
 //   origin + (x + 1/2 + t e_i) h,  t = u(x) / (u(x) - u(x + e_i)),
 // is written as float4 (X, Y, Z, i).  Two passes make the output order
 // deterministic (voxel index ascending, then axis): pass 1 counts per
-// workgroup, a one-workgroup scan turns counts into offsets, pass 2
+// workgroup, a scan turns the counts into offsets (each scan workgroup
+// scans 1024 counts, one more workgroup scans their totals), pass 2
 // recomputes and writes each point at its rank.
 #include "internal.h"
 
 namespace tgv {
 
 constexpr int EXT_THREADS = 256;
+constexpr int SCAN_THREADS = 1024;
 
 // bit i of the result is set when edge (x, x + e_i) changes sign; t[i] is
 // its crossing parameter (NaN if an end value is NaN)
@@ -42,7 +44,8 @@ __global__ void __launch_bounds__(EXT_THREADS) k_count_crossings(const float *__
     const long long idx = (long long)blockIdx.x * EXT_THREADS + threadIdx.x;
     int c = 0;
     if (idx < d.n) {
-        const int x = (int)(idx % d.nx), y = (int)((idx / d.nx) % d.ny), z = (int)(idx / d.sz);
+        const unsigned i = (unsigned)idx, nx = (unsigned)d.nx, row = i / nx;
+        const int x = (int)(i - row * nx), y = (int)(row % (unsigned)d.ny), z = (int)(row / (unsigned)d.ny);
         float t[3];
         c = __popc(crossings_at(u, d, idx, x, y, z, t));
     }
@@ -56,43 +59,60 @@ __global__ void __launch_bounds__(EXT_THREADS) k_count_crossings(const float *__
     if (threadIdx.x == 0) counts[blockIdx.x] = s[0];
 }
 
-// exclusive scan of nblocks counts by one workgroup (sequential chunks of
-// EXT_THREADS, each scanned in LDS); offsets[nblocks] = total
-__global__ void __launch_bounds__(EXT_THREADS) k_scan_counts(const unsigned *__restrict__ counts, int nblocks,
-                                                             unsigned long long *__restrict__ offsets) {
-    __shared__ unsigned long long s[EXT_THREADS];
-    __shared__ unsigned long long carry;
-    if (threadIdx.x == 0) carry = 0;
+// inclusive scan of one value per thread of a SCAN_THREADS workgroup
+__device__ __forceinline__ unsigned long long block_scan(unsigned long long v, unsigned long long *s) {
+    s[threadIdx.x] = v;
     __syncthreads();
-    for (int base = 0; base < nblocks; base += EXT_THREADS) {
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {  // Hillis-Steele
+        const unsigned long long add = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    return s[threadIdx.x];
+}
+
+// offsets within each run of SCAN_THREADS counts, and the runs' totals
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_counts(const unsigned *__restrict__ counts, int nblocks,
+                                                              unsigned long long *__restrict__ offsets,
+                                                              unsigned long long *__restrict__ totals) {
+    __shared__ unsigned long long s[SCAN_THREADS];
+    const int i = blockIdx.x * SCAN_THREADS + threadIdx.x;
+    const unsigned long long v = i < nblocks ? counts[i] : 0ull;
+    const unsigned long long inc = block_scan(v, s);
+    if (i < nblocks) offsets[i] = inc - v;
+    if (threadIdx.x == SCAN_THREADS - 1) totals[blockIdx.x] = inc;
+}
+
+// exclusive scan of the runs' totals in place (one workgroup, chunks of
+// SCAN_THREADS); offsets[nblocks] = the number of points
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_totals(unsigned long long *__restrict__ totals, int nruns,
+                                                              unsigned long long *__restrict__ offsets, int nblocks) {
+    __shared__ unsigned long long s[SCAN_THREADS];
+    unsigned long long carry = 0;
+    for (int base = 0; base < nruns; base += SCAN_THREADS) {
         const int i = base + threadIdx.x;
-        const unsigned long long v = i < nblocks ? counts[i] : 0ull;
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < EXT_THREADS; off <<= 1) {  // inclusive Hillis-Steele scan
-            unsigned long long add = threadIdx.x >= off ? s[threadIdx.x - off] : 0ull;
-            __syncthreads();
-            s[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (i < nblocks) offsets[i] = carry + s[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == EXT_THREADS - 1) carry += s[EXT_THREADS - 1];
-        __syncthreads();
+        const unsigned long long v = i < nruns ? totals[i] : 0ull;
+        const unsigned long long inc = block_scan(v, s);
+        if (i < nruns) totals[i] = carry + inc - v;
+        carry += s[SCAN_THREADS - 1];
+        __syncthreads();  // everyone has read s before the next chunk writes it
     }
     if (threadIdx.x == 0) offsets[nblocks] = carry;
 }
 
 __global__ void __launch_bounds__(EXT_THREADS) k_write_crossings(const float *__restrict__ u, Dims d, tgv_grid g,
                                                                  const unsigned long long *__restrict__ offsets,
+                                                                 const unsigned long long *__restrict__ run_base,
                                                                  float4 *__restrict__ pts, long long max_points) {
     const long long idx = (long long)blockIdx.x * EXT_THREADS + threadIdx.x;
     int c = 0, mask = 0, x = 0, y = 0, z = 0;
     float t[3] = {0.0f, 0.0f, 0.0f};
     if (idx < d.n) {
-        x = (int)(idx % d.nx);
-        y = (int)((idx / d.nx) % d.ny);
-        z = (int)(idx / d.sz);
+        const unsigned i = (unsigned)idx, nx = (unsigned)d.nx, row = i / nx;
+        x = (int)(i - row * nx);
+        y = (int)(row % (unsigned)d.ny);
+        z = (int)(row / (unsigned)d.ny);
         mask = crossings_at(u, d, idx, x, y, z, t);
         c = __popc(mask);
     }
@@ -105,7 +125,7 @@ __global__ void __launch_bounds__(EXT_THREADS) k_write_crossings(const float *__
         s[threadIdx.x] += add;
         __syncthreads();
     }
-    unsigned long long k = offsets[blockIdx.x] + s[threadIdx.x] - c;
+    unsigned long long k = run_base[blockIdx.x / SCAN_THREADS] + offsets[blockIdx.x] + s[threadIdx.x] - c;
     const float cx = g.origin[0] + ((float)x + 0.5f) * g.h;
     const float cy = g.origin[1] + ((float)y + 0.5f) * g.h;
     const float cz = g.origin[2] + ((float)z + 0.5f) * g.h;
@@ -138,14 +158,17 @@ void launch_prolongate(const float *uc, const Dims &dc, float *uf, const Dims &d
 }
 
 int extract_blocks(const Dims &d) { return (int)((d.n + EXT_THREADS - 1) / EXT_THREADS); }
+int extract_runs(const Dims &d) { return (extract_blocks(d) + SCAN_THREADS - 1) / SCAN_THREADS; }
 
 void launch_extract(const float *u, const Dims &d, const tgv_grid &g, unsigned *counts, unsigned long long *offsets,
-                    float4 *pts, long long max_points, hipStream_t s) {
-    const int nb = extract_blocks(d);
+                    unsigned long long *runs, float4 *pts, long long max_points, hipStream_t s) {
+    const int nb = extract_blocks(d), nr = extract_runs(d);
     hipLaunchKernelGGL(k_count_crossings, dim3(nb), dim3(EXT_THREADS), 0, s, u, d, counts);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(EXT_THREADS), 0, s, counts, nb, offsets);
+    hipLaunchKernelGGL(k_scan_counts, dim3(nr), dim3(SCAN_THREADS), 0, s, counts, nb, offsets, runs);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(SCAN_THREADS), 0, s, runs, nr, offsets, nb);
     if (pts && max_points > 0)
-        hipLaunchKernelGGL(k_write_crossings, dim3(nb), dim3(EXT_THREADS), 0, s, u, d, g, offsets, pts, max_points);
+        hipLaunchKernelGGL(k_write_crossings, dim3(nb), dim3(EXT_THREADS), 0, s, u, d, g, offsets, runs, pts,
+                           max_points);
 }
 
 }  // namespace tgv

@@ -125,8 +125,9 @@ void launch_convert(const void *src, int src_storage, void *dst, int dst_storage
 
 PyrGeom pyr_geom(int W, int H);
 int extract_blocks(const Dims &d);
+int extract_runs(const Dims &d);
 void launch_prolongate(const float *uc, const Dims &dc, float *uf, const Dims &df, hipStream_t s);
 void launch_extract(const float *u, const Dims &d, const tgv_grid &g, unsigned *counts, unsigned long long *offsets,
-                    float4 *pts, long long max_points, hipStream_t s);
+                    unsigned long long *runs, float4 *pts, long long max_points, hipStream_t s);
 
 }  // namespace tgv

@@ -15,7 +15,11 @@ oracle can follow it exactly:
   block with the library defaults the benchmark uses;
 - the full 1000-iteration solve of the benchmark, in its tiled launch
   configuration, is bit-identical to the per-voxel kernels (whose parity
-  with the oracle the small-block tests establish)."""
+  with the oracle the small-block tests establish);
+- the rows that widen the path on the same block: histograms with
+  terrestrial scans (vote 5) on random voxels, TV-L1 on crops, and the
+  zero level of the solved block (count and the oracle's points of two
+  rows)."""
 import sys
 
 import numpy as np
@@ -133,3 +137,76 @@ def test_bench_solve_bit_identical_to_per_voxel_kernels(terrain):
         out.append(u.cpu().numpy())
     assert np.array_equal(out[0].view(np.uint32), out[2].view(np.uint32))
     assert np.array_equal(out[1].view(np.uint32), out[2].view(np.uint32))
+
+
+def test_scan_histograms_on_random_voxels_bit_exact(terrain):
+    """Four terrestrial 360-degree scans (six 1024^2 faces each, vote 5)
+    added to the 64 stereo maps: histograms of the whole block on random
+    voxels against the oracle."""
+    import paper_2107_14790_amd as tgv
+    ctx, sc = terrain["ctx"], terrain["sc"]
+    say("terrain scans: 4 scanners x 6 faces 1024^2")
+    sd, scams = scenes.terrain_scans(n=N, device="cuda")
+    depth = np.concatenate([sc.depth, sd])
+    cams = scenes.concat_cameras(sc.cams, scams)
+    H, W = depth.shape[1:]
+    pyr = ctx.build_pyramids(torch.from_numpy(depth).cuda())
+    hist = ctx.build_histograms(pyr, W, H, tgv.cameras_from(cams), terrain["g"])
+    got = hist.cpu().numpy().view(np.uint16)
+    rng = np.random.default_rng(2563)
+    vox = rng.choice(N ** 3, size=20000, replace=False)
+    say("oracle on 20000 random voxels x", len(cams), "maps")
+    ref, _ = oracle.histograms(scenes.Scene(depth, cams, sc.grid), oracle.pyramids(depth), vox=vox)
+    assert np.array_equal(got[vox], ref)
+    # the scans add votes of weight 5 near the ground under the scanners
+    assert (got[vox].astype(np.int64) - terrain["hist_np"][vox]).max() >= 5
+
+
+def test_tvl1_crops_match_oracle(terrain):
+    """The TV-L1 model (Eq. 1) on the whole block, 16 iterations with the
+    library defaults, against the oracle on crops (the same locality
+    argument as for TGV)."""
+    import paper_2107_14790_amd as tgv
+    ctx, g = terrain["ctx"], terrain["g"]
+    u = torch.zeros(N ** 3, device="cuda")
+    ctx.solve(g, terrain["hist"], u, tgv.Params(iters=ITERS, flags=tgv.FLAG_TVL1))
+    torch.cuda.synchronize()
+    u_gpu = u.cpu().numpy().reshape(N, N, N)
+    rng = np.random.default_rng(2564)
+    samples = surface_samples(terrain["vox"], terrain["vox_hist"], 2, rng)
+    samples = [tuple(min(max(c - 2, 0), N - 4) for c in s) for s in samples] + [(N - 4, 0, 120)]
+    radius = 2 * ITERS + 2
+    for s in samples:
+        lo, hi = crop_box(s, 4, radius)
+        csc, shape = crop_scene(terrain["sc"], lo, hi)
+        say("tvl1 crop", lo, hi)
+        h_ref, _ = oracle.histograms(csc, terrain["opyr"])
+        assert np.array_equal(terrain["hist_np"][crop_indices(lo, hi)], h_ref), "crop histograms"
+        st = oracle.solve(h_ref, shape, scenes.default_bins(), ITERS, tvl1=True)
+        uc = st.u.reshape(shape[2], shape[1], shape[0])
+        a = [s[i] - lo[i] for i in range(3)]
+        ref = uc[a[2]:a[2] + 4, a[1]:a[1] + 4, a[0]:a[0] + 4]
+        got = u_gpu[s[2]:s[2] + 4, s[1]:s[1] + 4, s[0]:s[0] + 4]
+        assert np.abs(got - ref).max() <= 1e-4, s
+
+
+def test_zero_level_of_the_solved_block(terrain):
+    """Crossings of the whole solved block (200 iterations): their number is
+    the number of sign-changing grid edges counted here independently, and
+    the oracle's points of the two bottom rows (y = 0, 1; the same origin,
+    so the same float32 arithmetic) are all among them, bit for bit."""
+    import paper_2107_14790_amd as tgv
+    ctx, g, sc = terrain["ctx"], terrain["g"], terrain["sc"]
+    u = torch.zeros(N ** 3, device="cuda")
+    ctx.solve(g, terrain["hist"], u, tgv.Params(iters=200))
+    pts = ctx.extract_crossings(g, u).cpu().numpy()
+    U = u.cpu().numpy().reshape(N, N, N)
+    pos = U > 0
+    edges = sum(int((pos.take(range(1, N), axis=ax) != pos.take(range(0, N - 1), axis=ax)).sum()) for ax in range(3))
+    say("zero level:", len(pts), "points, sign-changing edges", edges)
+    assert len(pts) == edges and edges > N * N
+    crop = np.ascontiguousarray(U[:, 0:2, :])
+    ref = oracle.crossings(crop.ravel(), (N, 2, N), sc.grid.origin, sc.grid.h)
+    assert len(ref) > 0
+    got = {r.tobytes() for r in pts.view(np.uint32)}
+    assert all(r.tobytes() in got for r in ref.view(np.uint32))

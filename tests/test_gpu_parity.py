@@ -431,7 +431,7 @@ def test_block_beyond_tiled_offsets_falls_back_correctly(ctx):
 # ---------------------------------------------------------------------------
 # zero-level points
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("shape", [(37, 29, 23), (64, 8, 9), (1, 1, 1), (300, 3, 2)])
+@pytest.mark.parametrize("shape", [(37, 29, 23), (64, 8, 9), (1, 1, 1), (300, 3, 2), (70, 64, 60)])
 def test_crossings_bit_exact(ctx, shape):
     say("crossings", shape)
     rng = np.random.default_rng(sum(shape))
@@ -446,6 +446,22 @@ def test_crossings_bit_exact(ctx, shape):
     ref = oracle.crossings(u, shape, origin, h)
     assert pts.shape == ref.shape
     assert np.array_equal(pts.view(np.uint32), ref.view(np.uint32))
+
+
+def test_crossings_into_preallocated_output(ctx):
+    import paper_2107_14790_amd as tgv
+    say("crossings into a preallocated output")
+    rng = np.random.default_rng(5)
+    shape = (40, 33, 17)
+    u = torch.from_numpy(rng.uniform(-1, 1, int(np.prod(shape))).astype(np.float32)).cuda()
+    g = tgv.grid_c((0.5, -1.0, 0.25), 0.125, shape, 0)
+    ref = ctx.extract_crossings(g, u)
+    out = torch.full((ref.shape[0] + 7, 4), -1.0, device="cuda")
+    got = ctx.extract_crossings(g, u, out=out)
+    assert torch.equal(got, ref)
+    assert torch.equal(out[ref.shape[0]:], torch.full((7, 4), -1.0, device="cuda"))  # rows past the count untouched
+    with pytest.raises(ValueError):
+        ctx.extract_crossings(g, u, out=torch.empty((ref.shape[0] - 1, 4), device="cuda"))
 
 
 def test_crossings_of_solved_sphere(ctx):
