@@ -39,6 +39,16 @@ __device__ __forceinline__ int crossings_at(const float *__restrict__ u, const D
     return c;
 }
 
+// sum over the wave of c in 0..3 (two ballots), and over the lanes below
+// this one
+__device__ __forceinline__ unsigned wave_sum(int c, unsigned &below) {
+    const unsigned long long b0 = __ballot(c & 1), b1 = __ballot(c & 2);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    below = (unsigned)(__popcll(b0 & lt) + 2 * __popcll(b1 & lt));
+    return (unsigned)(__popcll(b0) + 2 * __popcll(b1));
+}
+
 __global__ void __launch_bounds__(EXT_THREADS) k_count_crossings(const float *__restrict__ u, Dims d,
                                                                  unsigned *__restrict__ counts) {
     const long long idx = (long long)blockIdx.x * EXT_THREADS + threadIdx.x;
@@ -49,14 +59,16 @@ __global__ void __launch_bounds__(EXT_THREADS) k_count_crossings(const float *__
         float t[3];
         c = __popc(crossings_at(u, d, idx, x, y, z, t));
     }
-    __shared__ unsigned s[EXT_THREADS];
-    s[threadIdx.x] = c;
+    __shared__ unsigned ws[EXT_THREADS / 64];
+    unsigned below;
+    const unsigned w = wave_sum(c, below);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x / 64] = w;
     __syncthreads();
-    for (int off = EXT_THREADS / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int k = 0; k < EXT_THREADS / 64; k++) tot += ws[k];
+        counts[blockIdx.x] = tot;
     }
-    if (threadIdx.x == 0) counts[blockIdx.x] = s[0];
 }
 
 // inclusive scan of one value per thread of a SCAN_THREADS workgroup
@@ -116,16 +128,15 @@ __global__ void __launch_bounds__(EXT_THREADS) k_write_crossings(const float *__
         mask = crossings_at(u, d, idx, x, y, z, t);
         c = __popc(mask);
     }
-    __shared__ unsigned s[EXT_THREADS];
-    s[threadIdx.x] = c;
+    // rank of this voxel's first point: the points of the lower waves of
+    // the workgroup and of the lower lanes of this wave come first
+    __shared__ unsigned ws[EXT_THREADS / 64];
+    unsigned below;
+    const unsigned w = wave_sum(c, below);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x / 64] = w;
     __syncthreads();
-    for (int off = 1; off < EXT_THREADS; off <<= 1) {
-        unsigned add = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
-        __syncthreads();
-        s[threadIdx.x] += add;
-        __syncthreads();
-    }
-    unsigned long long k = run_base[blockIdx.x / SCAN_THREADS] + offsets[blockIdx.x] + s[threadIdx.x] - c;
+    for (int k = 0; k < (int)(threadIdx.x / 64); k++) below += ws[k];
+    unsigned long long k = run_base[blockIdx.x / SCAN_THREADS] + offsets[blockIdx.x] + below;
     const float cx = g.origin[0] + ((float)x + 0.5f) * g.h;
     const float cy = g.origin[1] + ((float)y + 0.5f) * g.h;
     const float cz = g.origin[2] + ((float)z + 0.5f) * g.h;
