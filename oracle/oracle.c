@@ -411,7 +411,8 @@ static void project(double *y[], int m, const double *wts, long x, double alpha)
 }
 
 /* With tvl1 set the TV-L1 model of Eq. 1 is solved instead: the same
- * iteration with v held at 0 and no q (K reduces to M.grad).
+ * iteration with v held at 0 and no q (K reduces to M.grad); v, vbar and q
+ * are set to 0 first, whatever the state held.
  *
  * Primal-dual iterations (first-order primal-dual method with
  * over-relaxation theta = 1) on the saddle-point form of Eq. 2:
@@ -434,6 +435,11 @@ void or_solve(int nx, int ny, int nz, int halo, const uint16_t *hist, int nbins,
     double *gv = (double *)malloc(sizeof(double) * 3 * n);
     const double w3[3] = {1.0, 1.0, 1.0};
     const double w6[6] = {1.0, 1.0, 1.0, 2.0, 2.0, 2.0};
+    if (tvl1) { /* Eq. 1 has no v and no q */
+        memset(v, 0, sizeof(double) * 3 * n);
+        memset(vbar, 0, sizeof(double) * 3 * n);
+        memset(q, 0, sizeof(double) * 6 * n);
+    }
     for (int it = 0; it < iters; it++) {
         /* dual ascent */
         or_apply_K(nx, ny, nz, ubar, vbar, kp, kq);

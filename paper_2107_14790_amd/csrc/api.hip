@@ -494,6 +494,17 @@ extern "C" tgv_status tgv_state_import(tgv_ctx *ctx, tgv_state *st, const float 
 // ===========================================================================
 // solve
 // ===========================================================================
+// TV-L1 (Eq. 1) has no v and no q: both iterates of each are set to 0, so
+// every kernel reads and writes zeros there (and the two-iteration kernel
+// can leave them alone)
+static void zero_vq(tgv_state *st, hipStream_t s) {
+    const long long n = st->n, sb = storage_bytes(st->storage);
+    for (int k = 0; k < 2; k++) {
+        launch_fill_bytes0(st->v[k], 3 * n * sb, s);
+        launch_fill_bytes0(st->q[k], 6 * n * sb, s);
+    }
+}
+
 static bool same_grid(const tgv_grid &a, const tgv_grid &b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.halo == b.halo;
 }
@@ -572,6 +583,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
     Coef cf = make_coef(*params, *bins);
     int N = params->iters;
     if (N > 0) {
+        if (cf.tvl1) zero_vq(st, s);
         // dual step from (x^n, x^{n-1}, y^n): y^{n+1}, in place
         {
             SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
@@ -690,6 +702,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
     // 1. dual step of every block (in place)
     for (int i = 0; i < n; i++) {
         tgv_state *st = states[i];
+        if (cf.tvl1) zero_vq(st, s);
         SolveBufs b = bufs_of(st, st->xc, st->yc, hist[i]);
         if (st->fresh) {
             b.xo_u = b.xc_u;

@@ -189,7 +189,9 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     // 16-bit fields: every lane loads every field (lanes outside the block
     // read column 0, as in the one-iteration kernel); masked-off 16-bit loads
     // made both kernels slower
-    const int lmask = STORE == 0 ? (in ? lm : 0) : LD2_ALL;
+    // TV-L1: v and q are zero in memory (the solve sets them so) and stay
+    // zero, so they are neither loaded (a skipped load reads 0) nor stored
+    const int lmask = (STORE == 0 ? (in ? lm : 0) : LD2_ALL) & (cf.tvl1 ? ~(LD2_V | LD2_Q) : ~0);
     const int e = active ? (py - y0 + 2) * EX + (px - x0 + 2) : 0;
     const bool mlo_x = px > 0, mlo_y = py > 0, mhi_x = px < d.nx - 1, mhi_y = py < d.ny - 1;
     const bool fxy = d.halo > 0 && (px < d.halo || py < d.halo || px >= d.nx - d.halo || py >= d.ny - d.halo);
@@ -421,9 +423,11 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
                 const int sv = sb - 1;
                 const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
                 Io2<0>::st<SCP>(wu, v4, o4, outB.u);
-                for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wv, vS, oS + c * comp, outB.v[c]);
+                if (!cf.tvl1)
+                    for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wv, vS, oS + c * comp, outB.v[c]);
                 for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wp, vS, oS + c * comp, outB.p[c]);
-                for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, oS + c * comp, outB.q[c]);
+                if (!cf.tvl1)
+                    for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, oS + c * comp, outB.q[c]);
             }
         }
         if (runA) dual(la, A, ap.f, s, bo);
