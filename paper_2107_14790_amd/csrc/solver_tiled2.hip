@@ -130,7 +130,11 @@ struct Stage {
 
 // Two fused iterations on tile (tix, tiy, tiz) of a block: Xc, Yc in, Xn, Yn
 // out.  Every thread of the workgroup must call it (it holds barriers).
-template <int STORE, int TY, int SCP>
+// TV: the TV-L1 model in float32 storage, whose v and q are zero in memory
+// (the solve sets them so) and stay zero: they are neither loaded (a
+// skipped load reads 0) nor stored.  Other TV-L1 solves run the TV = false
+// kernels, which read and write those zeros.
+template <int STORE, int TY, int SCP, bool TV = false>
 __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf<STORE> &Xc, const YBuf<STORE> &Yc,
                                           const XBuf<STORE> &Xn, const YBuf<STORE> &Yn,
                                           const uint16_t *__restrict__ hist, const Dims &d, const Coef &cf, int CZ,
@@ -189,9 +193,7 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     // 16-bit fields: every lane loads every field (lanes outside the block
     // read column 0, as in the one-iteration kernel); masked-off 16-bit loads
     // made both kernels slower
-    // TV-L1: v and q are zero in memory (the solve sets them so) and stay
-    // zero, so they are neither loaded (a skipped load reads 0) nor stored
-    const int lmask = (STORE == 0 ? (in ? lm : 0) : LD2_ALL) & (cf.tvl1 ? ~(LD2_V | LD2_Q) : ~0);
+    const int lmask = STORE == 0 ? ((in ? lm : 0) & (TV ? ~(LD2_V | LD2_Q) : ~0)) : LD2_ALL;
     const int e = active ? (py - y0 + 2) * EX + (px - x0 + 2) : 0;
     const bool mlo_x = px > 0, mlo_y = py > 0, mhi_x = px < d.nx - 1, mhi_y = py < d.ny - 1;
     const bool fxy = d.halo > 0 && (px < d.halo || py < d.halo || px >= d.nx - d.halo || py >= d.ny - d.halo);
@@ -423,10 +425,10 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
                 const int sv = sb - 1;
                 const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
                 Io2<0>::st<SCP>(wu, v4, o4, outB.u);
-                if (!cf.tvl1)
+                if (!TV)
                     for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wv, vS, oS + c * comp, outB.v[c]);
                 for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wp, vS, oS + c * comp, outB.p[c]);
-                if (!cf.tvl1)
+                if (!TV)
                     for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, oS + c * comp, outB.q[c]);
             }
         }
@@ -443,7 +445,7 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     }
 }
 
-template <int STORE, int TY, int SCP>
+template <int STORE, int TY, int SCP, bool TV = false>
 __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     k_fused2_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn, YBuf<STORE> Yn, const uint16_t *__restrict__ hist,
                    Dims d, Coef cf, int CZ, int ntx, int nty, int ntz) {
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     const int per = (nb + 7) / 8;
     const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (T >= nb) return;
-    run_tile2<STORE, TY, SCP>(la, lb, Xc, Yc, Xn, Yn, hist, d, cf, CZ, T % ntx, (T / ntx) % nty, T / (ntx * nty));
+    run_tile2<STORE, TY, SCP, TV>(la, lb, Xc, Yc, Xn, Yn, hist, d, cf, CZ, T % ntx, (T / ntx) % nty, T / (ntx * nty));
 }
 
 // Batched two-iteration pass: every tile of every block advances two
@@ -490,7 +492,7 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     }
 }
 
-template <int STORE, int TY, int SCP>
+template <int STORE, int TY, int SCP, bool TV = false>
 static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
     XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
     XBuf<STORE> Xo{b.xo_u, (typename Store<STORE>::T *)b.xo_v};
@@ -499,13 +501,14 @@ static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz
     int ntx = (d.nx + TX - 1) / TX, nty = (d.ny + TY - 1) / TY, ntz = (d.nz + cz - 1) / cz;
     int nb = ntx * nty * ntz;
     int per = (nb + 7) / 8;
-    hipLaunchKernelGGL((k_fused2_tiled<STORE, TY, SCP>), dim3(8 * per), dim3(TX * (TY + 5)), 0, s, Xc, Yc, Xo, Yo, b.hist,
-                       d, cf, cz, ntx, nty, ntz);
+    hipLaunchKernelGGL((k_fused2_tiled<STORE, TY, SCP, TV>), dim3(8 * per), dim3(TX * (TY + 5)), 0, s, Xc, Yc, Xo, Yo,
+                       b.hist, d, cf, cz, ntx, nty, ntz);
 }
 
 template <int STORE, int SCP>
 static void launch2_t(const SolveBufs &b, const Dims &d, const Coef &cf, int ty, int cz, hipStream_t s) {
     if (ty == 6) launch2_ty<STORE, 6, SCP>(b, d, cf, cz, s);
+    else if (ty == 7 && STORE == 0 && cf.tvl1) launch2_ty<STORE, 7, SCP, true>(b, d, cf, cz, s);
     else if (ty == 7) launch2_ty<STORE, 7, SCP>(b, d, cf, cz, s);
     else launch2_ty<STORE, 4, SCP>(b, d, cf, cz, s);
 }
