@@ -136,3 +136,44 @@ def test_fused2_terrain256_sampled_state(ctx):
     auto = run(ctx, shape, hist, u0, 0, tgv.Params(iters=7))  # the default picks FUSED2 here
     assert_same_state(ref, auto)
     assert_same_state(ref, got)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_fused2_tvl1_default_tile_bit_identical(ctx, storage):
+    """TV-L1 with the default 64 x 7 tile (in float32 its own kernel, which
+    moves no v or q) against one iteration per pass."""
+    import paper_2107_14790_amd as tgv
+    shape = (130, 21, 40)
+    say("tvl1 default tile", shape, "storage", storage)
+    hist, u0 = random_problem(shape, 77 + storage)
+    ref = run(ctx, shape, hist, u0, 1, tgv.Params(iters=13, storage=storage, flags=tgv.FLAG_TVL1,
+                                                   schedule=tgv.SCHED_FUSED))
+    got = run(ctx, shape, hist, u0, 1, tgv.Params(iters=13, storage=storage, flags=tgv.FLAG_TVL1,
+                                                   schedule=tgv.SCHED_FUSED2))
+    assert_same_state(ref, got)
+    assert not got["v"].any() and not got["q"].any()
+
+
+def test_tvl1_after_tgv_sets_v_and_q_to_zero(ctx):
+    """A TV-L1 solve of a state that holds a TGV iterate starts by setting v
+    and q to 0 (Eq. 1 has neither), on every schedule alike."""
+    import paper_2107_14790_amd as tgv
+    shape = (70, 30, 18)
+    hist_np, u0_np = random_problem(shape, 91)
+    n = int(np.prod(shape))
+    g = tgv.grid_c((0, 0, 0), 1.0, shape, 0)
+    hist = torch.from_numpy(hist_np.view(np.int16).reshape(n, 8)).cuda()
+    out = []
+    for sched in (tgv.SCHED_FUSED, tgv.SCHED_FUSED2, tgv.SCHED_SPLIT):
+        st = tgv.State(ctx, g)
+        st.reset(torch.from_numpy(u0_np).cuda())
+        ctx.solve(g, hist, None, tgv.Params(iters=10, schedule=sched), state=st)
+        mid = st.export()
+        ctx.solve(g, hist, None, tgv.Params(iters=9, schedule=sched, flags=tgv.FLAG_TVL1), state=st)
+        f = {k: v.cpu().numpy() for k, v in st.export().items()}
+        st.close()
+        assert mid["v"].abs().max().item() > 0 and mid["q"].abs().max().item() > 0
+        assert not f["v"].any() and not f["v_prev"].any() and not f["q"].any()
+        out.append(f)
+    assert_same_state(out[0], out[1])
+    assert_same_state(out[0], out[2])
