@@ -35,6 +35,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc2(const void *p, long long
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, (int)RSRC_WORD3);
 }
 
+// All fields of a state in one allocation of at most 2 GiB: one buffer
+// descriptor serves every field, each field's byte offset from `base` goes
+// into the scalar offset (frees the scalar registers of seven descriptors).
+// The 2 GiB bound keeps a skipped load (lane offset 2^31) past the end.
+struct Span {
+    const void *base;
+    int bytes;
+    int u0, v0, p0, q0;  // current iterate
+    int u1, v1, p1, q1;  // next iterate
+};
+
 template <int STORE>
 struct Io2;
 template <>
@@ -134,11 +145,11 @@ struct Stage {
 // (the solve sets them so) and stay zero: they are neither loaded (a
 // skipped load reads 0) nor stored.  Other TV-L1 solves run the TV = false
 // kernels, which read and write those zeros.
-template <int STORE, int TY, int SCP, bool TV = false>
+template <int STORE, int TY, int SCP, bool TV = false, bool UNI = false>
 __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf<STORE> &Xc, const YBuf<STORE> &Yc,
                                           const XBuf<STORE> &Xn, const YBuf<STORE> &Yn,
                                           const uint16_t *__restrict__ hist, const Dims &d, const Coef &cf, int CZ,
-                                          int tix, int tiy, int tiz) {
+                                          int tix, int tiy, int tiz, const Span &sp = Span{}) {
     using L = XLds<TY>;
     constexpr int EX = L::EX, NE = L::NE;
     constexpr int SB = STORE == 0 ? 4 : 2;
@@ -230,20 +241,32 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     const int v4 = (int)(col * 4), vS = (int)(col * SB), vH = (int)(col * 16);
     const int comp = (int)(d.n * SB);
     const long long plane4 = d.sz * 4, planeS = d.sz * SB, planeH = d.sz * 16;
-    const auto ru = rsrc2(Xc.u, d.n * 4), rv = rsrc2(Xc.v, 3 * d.n * SB), rp = rsrc2(Yc.p, 3 * d.n * SB),
-               rq = rsrc2(Yc.q, 6 * d.n * SB), rh = rsrc2(hist, d.n * 16);
-    const auto wu = rsrc2(Xn.u, d.n * 4), wv = rsrc2(Xn.v, 3 * d.n * SB), wp = rsrc2(Yn.p, 3 * d.n * SB),
-               wq = rsrc2(Yn.q, 6 * d.n * SB);
+    const auto rh = rsrc2(hist, d.n * 16);
+    __amdgpu_buffer_rsrc_t ru, rv, rp, rq, wu, wv, wp, wq;
+    int fu = 0, fv = 0, fp = 0, fq = 0, gu = 0, gv = 0, gp = 0, gq = 0;  // field offsets (one descriptor)
+    if constexpr (UNI) {
+        const auto rs = rsrc2(sp.base, sp.bytes);
+        ru = rv = rp = rq = wu = wv = wp = wq = rs;
+        fu = sp.u0; fv = sp.v0; fp = sp.p0; fq = sp.q0;
+        gu = sp.u1; gv = sp.v1; gp = sp.p1; gq = sp.q1;
+    } else {
+        ru = rsrc2(Xc.u, d.n * 4); rv = rsrc2(Xc.v, 3 * d.n * SB); rp = rsrc2(Yc.p, 3 * d.n * SB);
+        rq = rsrc2(Yc.q, 6 * d.n * SB);
+        wu = rsrc2(Xn.u, d.n * 4); wv = rsrc2(Xn.v, 3 * d.n * SB); wp = rsrc2(Yn.p, 3 * d.n * SB);
+        wq = rsrc2(Yn.q, 6 * d.n * SB);
+    }
 
     auto load_state = [&](Pl &P, uint32_t hw[4], int s) {
         const int sc = s < d.nz ? s : d.nz - 1;
         const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
         const int m = lmask;
-        P.u = Io2<0>::ld(ru, (m & LD2_U) ? v4 : LD2_SKIP, o4);
+        P.u = Io2<0>::ld(ru, (m & LD2_U) ? v4 : LD2_SKIP, o4 + fu);
         const int ov = (m & LD2_V) ? vS : LD2_SKIP;
-        for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE>::ld(rv, ov, oS + c * comp);
-        for (int c = 0; c < 3; c++) P.p[c] = Io2<STORE>::ld(rp, (m & (LD2_PX << c)) ? vS : LD2_SKIP, oS + c * comp);
-        for (int c = 0; c < 6; c++) P.q[c] = Io2<STORE>::ld(rq, (m & (LD2_Q0 << c)) ? vS : LD2_SKIP, oS + c * comp);
+        for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE>::ld(rv, ov, fv + oS + c * comp);
+        for (int c = 0; c < 3; c++)
+            P.p[c] = Io2<STORE>::ld(rp, (m & (LD2_PX << c)) ? vS : LD2_SKIP, fp + oS + c * comp);
+        for (int c = 0; c < 6; c++)
+            P.q[c] = Io2<STORE>::ld(rq, (m & (LD2_Q0 << c)) ? vS : LD2_SKIP, fq + oS + c * comp);
         auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, (m & LD2_H) ? vH : LD2_SKIP, oH, 0);
         hw[0] = hv[0];
         hw[1] = hv[1];
@@ -424,12 +447,12 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
             if (dual(lb, B, bp, sb, outB) && in) {
                 const int sv = sb - 1;
                 const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
-                Io2<0>::st<SCP>(wu, v4, o4, outB.u);
+                Io2<0>::st<SCP>(wu, v4, o4 + gu, outB.u);
                 if (!TV)
-                    for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wv, vS, oS + c * comp, outB.v[c]);
-                for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wp, vS, oS + c * comp, outB.p[c]);
+                    for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wv, vS, gv + oS + c * comp, outB.v[c]);
+                for (int c = 0; c < 3; c++) Io2<STORE>::template st<SCP>(wp, vS, gp + oS + c * comp, outB.p[c]);
                 if (!TV)
-                    for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, oS + c * comp, outB.q[c]);
+                    for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, gq + oS + c * comp, outB.q[c]);
             }
         }
         if (runA) dual(la, A, ap.f, s, bo);
@@ -445,17 +468,18 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     }
 }
 
-template <int STORE, int TY, int SCP, bool TV = false>
+template <int STORE, int TY, int SCP, bool TV = false, bool UNI = false>
 __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     k_fused2_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn, YBuf<STORE> Yn, const uint16_t *__restrict__ hist,
-                   Dims d, Coef cf, int CZ, int ntx, int nty, int ntz) {
+                   Dims d, Coef cf, int CZ, int ntx, int nty, int ntz, Span sp) {
     __shared__ XLds<TY> la, lb;
     // XCD-aware tile order, as in the one-iteration kernel
     const int nb = ntx * nty * ntz;
     const int per = (nb + 7) / 8;
     const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (T >= nb) return;
-    run_tile2<STORE, TY, SCP, TV>(la, lb, Xc, Yc, Xn, Yn, hist, d, cf, CZ, T % ntx, (T / ntx) % nty, T / (ntx * nty));
+    run_tile2<STORE, TY, SCP, TV, UNI>(la, lb, Xc, Yc, Xn, Yn, hist, d, cf, CZ, T % ntx, (T / ntx) % nty,
+                                       T / (ntx * nty), sp);
 }
 
 // Batched two-iteration pass: every tile of every block advances two
@@ -492,6 +516,26 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     }
 }
 
+// the one-descriptor form when every field lies within 2 GiB of the lowest
+static bool state_span(const SolveBufs &b, const Dims &d, int sb, Span &sp) {
+    const char *f[8] = {(const char *)b.xc_u, (const char *)b.xc_v, (const char *)b.yc_p, (const char *)b.yc_q,
+                        (const char *)b.xo_u, (const char *)b.xo_v, (const char *)b.yo_p, (const char *)b.yo_q};
+    const long long len[8] = {4 * d.n, 3 * d.n * sb, 3 * d.n * sb, 6 * d.n * sb,
+                              4 * d.n, 3 * d.n * sb, 3 * d.n * sb, 6 * d.n * sb};
+    const char *lo = f[0];
+    const char *hi = f[0] + len[0];
+    for (int k = 1; k < 8; k++) {
+        lo = f[k] < lo ? f[k] : lo;
+        hi = f[k] + len[k] > hi ? f[k] + len[k] : hi;
+    }
+    if (hi - lo >= (1LL << 31)) return false;
+    sp.base = lo;
+    sp.bytes = (int)(hi - lo);
+    int *o[8] = {&sp.u0, &sp.v0, &sp.p0, &sp.q0, &sp.u1, &sp.v1, &sp.p1, &sp.q1};
+    for (int k = 0; k < 8; k++) *o[k] = (int)(f[k] - lo);
+    return true;
+}
+
 template <int STORE, int TY, int SCP, bool TV = false>
 static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz, hipStream_t s) {
     XBuf<STORE> Xc{b.xc_u, (typename Store<STORE>::T *)b.xc_v};
@@ -501,8 +545,13 @@ static void launch2_ty(const SolveBufs &b, const Dims &d, const Coef &cf, int cz
     int ntx = (d.nx + TX - 1) / TX, nty = (d.ny + TY - 1) / TY, ntz = (d.nz + cz - 1) / cz;
     int nb = ntx * nty * ntz;
     int per = (nb + 7) / 8;
-    hipLaunchKernelGGL((k_fused2_tiled<STORE, TY, SCP, TV>), dim3(8 * per), dim3(TX * (TY + 5)), 0, s, Xc, Yc, Xo, Yo,
-                       b.hist, d, cf, cz, ntx, nty, ntz);
+    Span sp{};
+    if (STORE == 0 && TY == 7 && state_span(b, d, 4, sp))
+        hipLaunchKernelGGL((k_fused2_tiled<STORE, TY, SCP, TV, (STORE == 0 && TY == 7)>), dim3(8 * per),
+                           dim3(TX * (TY + 5)), 0, s, Xc, Yc, Xo, Yo, b.hist, d, cf, cz, ntx, nty, ntz, sp);
+    else
+        hipLaunchKernelGGL((k_fused2_tiled<STORE, TY, SCP, TV>), dim3(8 * per), dim3(TX * (TY + 5)), 0, s, Xc, Yc, Xo,
+                           Yo, b.hist, d, cf, cz, ntx, nty, ntz, sp);
 }
 
 template <int STORE, int SCP>
