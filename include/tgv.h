@@ -101,18 +101,19 @@ enum { TGV_STORE_F32 = 0, TGV_STORE_F16 = 1, TGV_STORE_BF16 = 2 };
  * 64 x 7 tiles with the chunk depth chosen for the device); AUTO runs FUSED2
  * for a block whose iteration moves more than 48 MiB (when tile_y is 0)
  * and FUSED otherwise.  All of them produce bit-identical results.  A
- * batched solve always runs its persistent one-iteration kernel, whatever
- * the schedule. */
+ * batched solve runs two iterations per persistent launch with FUSED2, and
+ * with AUTO when tile_y is 0; one per launch otherwise. */
 enum { TGV_SCHED_FUSED = 0, TGV_SCHED_SPLIT = 1, TGV_SCHED_FUSED_REF = 2, TGV_SCHED_FUSED2 = 3, TGV_SCHED_AUTO = 4 };
 
 /* Solver parameters (Eq. 2, Sec. 3.2).  tau, sigma: primal and dual step
  * sizes (> 0); iters >= 0 primal-dual iterations.  tile_y, tile_z: shape of
  * the fused kernel's tiles (64 x tile_y columns, tile_z planes per
  * workgroup); 0 picks the library default: tile_y 8 for a float32 block
- * whose iteration moves more than 256 MiB, else 4; 7 for FUSED2; 4 for a
- * batched solve (tile_y in {4, 8, 12}; in {4, 6, 7} for FUSED2); tile_z
+ * whose iteration moves more than 256 MiB, else 4; 7 for FUSED2 (and for
+ * a batched solve that runs two iterations per launch); 4 for a batched
+ * solve with one (tile_y in {4, 8, 12}; in {4, 6, 7} for FUSED2); tile_z
  * from a model of the launch's rounds of resident workgroups (up to 32
- * planes for FUSED; 32 for a batched solve). */
+ * planes for FUSED; at most 32 for a batched solve). */
 typedef struct {
     float alpha0, alpha1, lambda;
     float tau, sigma;
@@ -246,10 +247,11 @@ tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, c
 
 /* Batched solve (many uneven blocks, Sec. 4.5: treetop leaves are
  * independent units, and small ones are processed together): advance each
- * of the n states by params->iters iterations.  Every iteration of all
- * blocks is one persistent launch whose workgroups pull tiles from a device
- * work queue (plus a per-block dual step at the start and primal step at
- * the end).  hist: host array of n device pointers (block i's histograms);
+ * of the n states by params->iters iterations.  Every iteration (or
+ * pair of iterations, see the schedules) of all blocks is one persistent
+ * launch whose workgroups pull tiles from a device work queue (plus a
+ * per-block dual step at the start and primal step at the end; blocks too
+ * large for 32-bit tile offsets run their own per-voxel launches).  hist: host array of n device pointers (block i's histograms);
  * tile_z_host: per-block z-chunk of the tiles (NULL = params->tile_z or the
  * default); params->tile_y applies to all blocks.  With TGV_FLAG_GRAPH the
  * iteration loop is captured once in a HIP graph and replayed.  Results are
