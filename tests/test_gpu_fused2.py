@@ -177,3 +177,28 @@ def test_tvl1_after_tgv_sets_v_and_q_to_zero(ctx):
         out.append(f)
     assert_same_state(out[0], out[1])
     assert_same_state(out[0], out[2])
+
+
+def test_fused2_on_caller_memory_and_a_large_state(ctx):
+    """The two-iteration kernel on a state in caller memory (a torch tensor,
+    as the server uses) and on a 2.2 GiB float32 state (beyond the one-
+    descriptor form) equals one iteration per pass."""
+    import paper_2107_14790_amd as tgv
+    for shape, wrapped in (((130, 50, 41), True), ((272, 272, 288), False)):
+        say("caller memory" if wrapped else "state above 2 GiB", shape)
+        n = int(np.prod(shape))
+        g = tgv.grid_c((0, 0, 0), 1.0, shape, 0)
+        rng = np.random.default_rng(n % 1000)
+        hist = torch.zeros((n, 8), dtype=torch.int16, device="cuda")
+        hist[:, :7] = torch.from_numpy(rng.integers(0, 3, size=(n, 7)).astype(np.int16)).cuda()
+        outs = []
+        for sched in (tgv.SCHED_FUSED, tgv.SCHED_FUSED2):
+            mem = torch.empty(tgv.state_bytes(g) // 4 + 64, dtype=torch.float32, device="cuda") if wrapped else None
+            st = tgv.State(ctx, g, memory=mem)
+            assert (st.bytes() > (1 << 31)) == (not wrapped)
+            st.reset(torch.zeros(n, device="cuda"))
+            ctx.solve(g, hist, None, tgv.Params(iters=4, schedule=sched), state=st)
+            outs.append(st.export()["u"].cpu())
+            st.close()
+            del mem
+        assert torch.equal(outs[0].view(torch.int32), outs[1].view(torch.int32))
