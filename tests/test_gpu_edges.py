@@ -95,3 +95,19 @@ def test_field_without_zero_level_has_no_crossings(ctx):
     n = 33 * 17 * 9
     for u in (torch.ones(n, device="cuda"), -torch.ones(n, device="cuda"), torch.zeros(n, device="cuda")):
         assert ctx.extract_crossings(g, u).shape == (0, 4)
+
+
+def test_large_depth_maps_histograms_bit_exact(ctx):
+    """2048 x 2048 depth maps (12 pyramid levels; the precision workload's
+    size) on a 48^3 block, with the voxels coarse enough to read from
+    several levels: histograms bit for bit against the oracle."""
+    import paper_2107_14790_amd as tgv
+    say("2048^2 maps")
+    sc = scenes.terrain_scene(n=48, n_side=2, W=2048, H=2048, f=3072.0, lattice=512, device="cuda")
+    H, W = sc.depth.shape[1:]
+    pyr = ctx.build_pyramids(torch.from_numpy(sc.depth).cuda())
+    opyr = oracle.pyramids(sc.depth)
+    assert np.array_equal(pyr.cpu().numpy().reshape(-1).view(np.uint32), opyr.view(np.uint32))
+    hist = ctx.build_histograms(pyr, W, H, sc.cams, tgv.grid_from(sc.grid)).cpu().numpy().view(np.uint16)
+    ref, _ = oracle.histograms(sc, opyr)
+    assert np.array_equal(hist, ref) and ref.sum() > 0
