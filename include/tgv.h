@@ -127,8 +127,9 @@ typedef struct {
 /* flags: TGV_FLAG_GRAPH captures a batched solve's iteration loop in a HIP
  * graph and replays it; TGV_FLAG_TVL1 solves the TV-L1 model of Eq. 1
  * (alpha1 |grad u| + lambda data, i.e. v held at 0 and q unused) instead of
- * the TGV model of Eq. 2: the solve first sets the state's v and q (both
- * iterates) to 0, whatever they held, and they stay 0. */
+ * the TGV model of Eq. 2: a solve of at least one iteration first sets the
+ * state's v and q (both iterates) to 0, whatever they held, and they stay
+ * 0. */
 enum { TGV_FLAG_GRAPH = 1, TGV_FLAG_TVL1 = 2 };
 
 /* Energy statistics of a state, reduced in float64:
