@@ -394,12 +394,14 @@ def prolongate(u_coarse, coarse_shape, fine_shape) -> np.ndarray:
 
 
 def coarse_to_fine(scene, levels, iters, alpha0=2.0, alpha1=1.0, lam=1.0, tau=None, sigma=None, num_bins=7,
-                   rule=0, centers=None):
+                   rule=0, centers=None, record=None):
     """Solve the block on levels-1 .. 0 with voxel size h 2^k (ceil(n / 2^k)
     voxels per axis, same origin, delta scaled with the voxel): each level's
     histograms come from the depth maps, its start value is the prolongated
     coarser solution (0 on the coarsest) and its border layer (the finest
-    level's halo; none on coarser levels) stays frozen."""
+    level's halo; none on coarser levels) stays frozen.  When `record` is a
+    list, one dict per level (coarsest first) is appended to it: the level
+    k, its grid, delta, histograms, start value u0 and result u."""
     g0 = scene.grid
     grids = [_Grid(g0.origin, g0.h, g0.n, g0.halo)]
     for k in range(1, levels):
@@ -418,4 +420,6 @@ def coarse_to_fine(scene, levels, iters, alpha0=2.0, alpha1=1.0, lam=1.0, tau=No
         u0 = np.zeros(gk.nvox) if u is None else prolongate(u, grids[k + 1].n, gk.n)
         st = solve(hk, gk.n, centers, iters, alpha0, alpha1, lam, tau, sigma, halo=gk.halo, num_bins=num_bins, u0=u0)
         u = st.u
+        if record is not None:
+            record.append(dict(k=k, grid=gk, delta=float(delta0 * np.float32(2 ** k)), hist=hk, u0=u0, u=u.copy()))
     return u

@@ -455,3 +455,167 @@ def test_tvl1_gap_closes():
     st = oracle.solve(hist, shape, C7, 20000, tvl1=True)
     P, D, g = oracle.gap(hist, shape, C7, st, tvl1=True)
     assert D <= P + 1e-9 and g < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# coarse-to-fine levels (Sec. 3.2: coarse-to-fine iterations; Sec. 3.1: the
+# band width delta = 6 r scales with the voxel; Sec. 4.5 / Fig. 7: a finer
+# part starts from, and freezes its border to, the parent level's indicator)
+# ---------------------------------------------------------------------------
+def _plane_level_bins(zpi, k, nz_k):
+    """Expected rule-0 bin of each coarse z-index of level k for the plane of
+    plane_scene(z_plane_index=zpi), worked out by hand: level k has voxel
+    edge 2^k h and the same origin, so its centre c sits at (c + 1/2) 2^k h
+    and the plane at (zpi + 1/2) h; the offset in the level's own voxels is
+    d = (zpi + 1/2) / 2^k - (c + 1/2), and with delta = 3 voxels of that
+    level a / delta = d / 3, whose nearest of linspace(-1, 1, 7) is
+    floor(d + 3.5) for |d| <= 3 (Alg. 1 clamp, rule 0)."""
+    out = []
+    for c in range(nz_k):
+        d = (zpi + 0.5) / 2 ** k - (c + 0.5)
+        assert abs((d % 1.0) - 0.5) > 0.1, "offset on a bin boundary: the case would test rounding"
+        assert abs(d) <= 3
+        out.append(int(np.floor(d + 3.5)))
+    return out
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_coarse_to_fine_levels_follow_the_scaled_plane(levels):
+    """Each level of the oracle's coarse-to-fine solve sees the geometry a
+    hand computation gives (origin kept, voxel h 2^k, ceil(n / 2^k) voxels,
+    delta = 3 h 2^k), its histograms are the plane rule at that scale, its
+    solution is the level's own affine indicator (zero TGV energy, the unique
+    minimiser), and the finest level returns the plane to 1e-6."""
+    zpi = 3.0
+    sc = scenes.plane_scene(n=(4, 3, 7), z_plane_index=zpi, n_cams=3)
+    rec = []
+    u = oracle.coarse_to_fine(sc, levels, 3000, record=rec)
+    assert [r["k"] for r in rec] == list(range(levels - 1, -1, -1))
+    expect_n = {0: (4, 3, 7), 1: (2, 2, 4), 2: (1, 1, 2)}
+    expect_h = {0: 0.25, 1: 0.5, 2: 1.0}
+    for r in rec:
+        k, g = r["k"], r["grid"]
+        assert g.n == expect_n[k] and g.h == expect_h[k]
+        np.testing.assert_array_equal(g.origin, sc.grid.origin)
+        assert r["delta"] == 0.75 * 2 ** k
+        nx, ny, nz = g.n
+        H = r["hist"].reshape(nz, ny, nx, 8)
+        bins = _plane_level_bins(zpi, k, nz)
+        for c, b in enumerate(bins):
+            expect = np.zeros(8, dtype=np.uint16)
+            expect[b] = 3  # three cameras, vote 1 each
+            assert (H[c] == expect).all(), (k, c, H[c, 0, 0], b)
+        uk = r["u"].reshape(nz, ny, nx)
+        want = np.array([C64[b] for b in bins])
+        np.testing.assert_allclose(uk, np.broadcast_to(want[:, None, None], uk.shape), atol=1e-6)
+        if k == levels - 1:
+            assert not r["u0"].any()  # the coarsest level starts from 0
+        else:
+            # the start value is the parent level's result, cube by cube
+            parent = rec[[q["k"] for q in rec].index(k + 1)]
+            pn = parent["grid"].n
+            U0 = r["u0"].reshape(nz, ny, nx)
+            P = parent["u"].reshape(pn[2], pn[1], pn[0])
+            for (z, y, x) in [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz // 2, 0, nx - 1)]:
+                assert U0[z, y, x] == P[z // 2, y // 2, x // 2]
+    np.testing.assert_allclose(u.reshape(7, 3, 4), np.broadcast_to(C64[[6, 5, 4, 3, 2, 1, 0]][:, None, None],
+                                                                   (7, 3, 4)), atol=1e-6)
+
+
+def test_coarse_to_fine_freezes_only_the_finest_border_to_the_parent():
+    """With a 1-voxel halo on the block, the finest level keeps its border at
+    the prolongated level-1 solution (known by hand: c_bin of the parent
+    cube), while level 1 itself has no frozen layer (it reaches its affine
+    indicator up to its faces)."""
+    zpi = 3.0
+    sc = scenes.plane_scene(n=(4, 3, 7), z_plane_index=zpi, n_cams=3)
+    sc.grid = scenes.Grid(sc.grid.origin, sc.grid.h, sc.grid.n, 1)
+    rec = []
+    u = oracle.coarse_to_fine(sc, 2, 3000, record=rec)
+    lvl1, lvl0 = rec
+    assert lvl1["grid"].halo == 0 and lvl0["grid"].halo == 1
+    parent_bins = _plane_level_bins(zpi, 1, 4)  # [4, 3, 2, 1]
+    U = u.reshape(7, 3, 4)
+    z, y, x = np.meshgrid(np.arange(7), np.arange(3), np.arange(4), indexing="ij")
+    frozen = (x < 1) | (x >= 3) | (y < 1) | (y >= 2) | (z < 1) | (z >= 6)
+    want_frozen = np.array([C64[parent_bins[k // 2]] for k in range(7)])[z]
+    np.testing.assert_allclose(U[frozen], want_frozen[frozen], atol=1e-6)
+    # the border is exactly the start value (never updated)
+    np.testing.assert_array_equal(U[frozen], lvl0["u0"].reshape(7, 3, 4)[frozen])
+
+
+# ---------------------------------------------------------------------------
+# energies with a frozen border (Sec. 4.5, Fig. 7: u is fixed on set B, so
+# the data term counts free voxels only and the dual pays u.(K^T p) there)
+# ---------------------------------------------------------------------------
+def _frozen_mask(shape, halo):
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    m = (x < halo) | (x >= nx - halo) | (y < halo) | (y >= ny - halo) | (z < halo) | (z >= nz - halo)
+    return m.ravel()
+
+
+@pytest.mark.parametrize("halo", [1, 2])
+def test_weak_duality_with_a_frozen_border(halo):
+    """D(p, q) <= P(u, v) for every feasible pair of the problem with u fixed
+    on the border: u in [-1, 1] on free voxels, |v| <= 2 sqrt 3, |p| <= a1,
+    |q| <= a0 (Frobenius).  Random points, random frozen values."""
+    rng = np.random.default_rng(40 + halo)
+    shape = (7, 6, 5)
+    n = 210
+    hist = rand_hist(shape, rng, fully=False)
+    for _ in range(30):
+        u = rng.uniform(-1, 1, n)
+        v = rng.normal(size=(3, n)) * rng.uniform(0.1, 3.0)
+        v = (v / np.maximum(1.0, np.linalg.norm(v, axis=0) / oracle.VBOUND)).ravel()
+        p = rng.normal(size=(3, n))
+        p = (p / np.maximum(1.0, np.linalg.norm(p, axis=0))).ravel()
+        q = rng.normal(size=(6, n))
+        qn = np.sqrt((q[:3] ** 2).sum(0) + 2 * (q[3:] ** 2).sum(0))
+        q = (q / np.maximum(1.0, qn / 2.0)).ravel()
+        P, _ = oracle.primal_energy(hist, shape, C7, u, v, halo=halo)
+        D = oracle.dual_energy(hist, shape, C7, u, p, q, halo=halo)
+        assert D <= P + 1e-9
+
+
+def test_gap_closes_with_the_border_frozen_at_the_minimiser():
+    """Constant histograms (weighted median c_4 = 1/3, odd total) and a 1-voxel
+    border frozen at that median: u = 1/3, v = 0 is the minimiser, its energy
+    is the data term of the free voxels only (4^3 of them), and the gap
+    closes.  A data term counted on frozen voxels would leave P above D by
+    the frozen voxels' data."""
+    shape = (6, 6, 6)
+    n = 216
+    hist = np.zeros((n, 8), dtype=np.uint16)
+    hist[:, :7] = [1, 0, 2, 0, 3, 1, 0]  # W = 7; sorted: c0 c2 c2 c4 c4 c4 c5 -> median c4
+    m = np.float64(C7[4])
+    frozen = _frozen_mask(shape, 1)
+    assert frozen.sum() == 216 - 64
+    st = oracle.solve(hist, shape, C7, 4000, halo=1, u0=np.full(n, m))
+    np.testing.assert_allclose(st.u, m, atol=1e-9)
+    data_one = sum(int(hist[0, k]) * abs(m - np.float64(C7[k])) for k in range(7))
+    P, parts = oracle.primal_energy(hist, shape, C7, st.u, st.v, halo=1)
+    assert abs(parts[2] - 64 * data_one) <= 1e-9 * 64 * data_one
+    P, D, g = oracle.gap(hist, shape, C7, st, halo=1)
+    assert D <= P + 1e-9 and g < 1e-6
+
+
+@pytest.mark.parametrize("halo", [1, 2])
+def test_gap_closes_with_a_random_frozen_border(halo):
+    """Random histograms on every voxel and a border frozen at random values
+    in [-1, 1]: the minimiser pulls against the border, so p is non-zero
+    there and the dual's frozen term u.(K^T p) matters; at convergence the
+    primal and dual energies meet (a sign error in that term, or data counted
+    on frozen voxels, would keep them apart)."""
+    rng = np.random.default_rng(50 + halo)
+    shape = (8, 7, 6) if halo == 1 else (9, 8, 8)
+    n = int(np.prod(shape))
+    hist = rand_hist(shape, rng, odd=True)
+    u0 = np.where(_frozen_mask(shape, halo), rng.uniform(-1, 1, n), 0.0)
+    st = oracle.solve(hist, shape, C7, 40000, halo=halo, u0=u0)
+    frozen = _frozen_mask(shape, halo)
+    np.testing.assert_array_equal(st.u[frozen], u0[frozen])
+    gu, _ = oracle.apply_KT(st.p, st.q, shape)
+    assert np.abs(gu[frozen]).max() > 0.1  # the border term is really exercised
+    P, D, g = oracle.gap(hist, shape, C7, st, halo=halo)
+    assert D <= P + 1e-9 and g < 1e-6, (P, D, g)
