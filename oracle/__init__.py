@@ -53,10 +53,15 @@ def lib():
         L.or_pyramid.argtypes = [_f32p, c_int, c_int, _f32p]
         L.or_pyramid.restype = None
         L.or_vote_bin.argtypes = [_f32p, c_int, c_int, _f32p, _f32p, _f32p, _f32p, c_float, c_int, c_int, c_int,
-                                  c_float, c_float, c_int, c_int]
+                                  c_float, c_float, c_int, c_int, c_int, ctypes.c_void_p]
         L.or_vote_bin.restype = c_int
-        L.or_histograms.argtypes = [_f32p, c_int, _f32p, _f32p, _f32p, _i32p, _i32p, _f32p, c_float, c_int, c_int,
-                                    c_int, c_float, c_float, c_int, c_int, ctypes.c_void_p, c_long, _u16p]
+        L.or_scan_tables.argtypes = [c_int, c_int, _f32p, _f32p, _f32p]
+        L.or_scan_tables.restype = None
+        L.or_scan_pixel.argtypes = [c_float, c_float, c_float, c_float, c_int, c_int, _f32p, _f32p, _f32p,
+                                    ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+        L.or_scan_pixel.restype = None
+        L.or_histograms.argtypes = [_f32p, c_int, _f32p, _f32p, _f32p, _i32p, _i32p, _i32p, _f32p, c_float, c_int,
+                                    c_int, c_int, c_float, c_float, c_int, c_int, ctypes.c_void_p, c_long, _u16p]
         L.or_histograms.restype = c_long
         L.or_apply_K.argtypes = [c_int, c_int, c_int, _f64p, _f64p, _f64p, _f64p]
         L.or_apply_K.restype = None
@@ -178,9 +183,35 @@ def histograms(scene, pyr=None, vox=None, num_bins=7, rule=0, delta=None, eta_ov
                              np.ascontiguousarray(cams.intr.reshape(-1), dtype=np.float32),
                              np.ascontiguousarray(cams.wh.reshape(-1), dtype=np.int32),
                              np.ascontiguousarray(cams.vote, dtype=np.int32),
+                             np.ascontiguousarray(camera_models(cams), dtype=np.int32),
                              np.ascontiguousarray(g.origin, dtype=np.float32), float(g.h), nx, ny, nz,
                              bp["delta"], bp["eta_over_delta"], bp["num_bins"], bp["rule"], vptr, count, out)
     return out, int(mx)
+
+
+def camera_models(cams) -> np.ndarray:
+    """Per-camera model: 0 pinhole depth map, 1 equirectangular 360-degree scan."""
+    m = getattr(cams, "model", None)
+    return np.zeros(len(cams), dtype=np.int32) if m is None else np.asarray(m, dtype=np.int32)
+
+
+def scan_tables(W: int, H: int):
+    """The column (C, S: W/4 each) and row (K: H) boundary tables of a W x H
+    equirectangular scan (float32)."""
+    C = np.empty(W // 4, dtype=np.float32)
+    S = np.empty(W // 4, dtype=np.float32)
+    K = np.empty(H, dtype=np.float32)
+    lib().or_scan_tables(W, H, C, S, K)
+    return C, S, K
+
+
+def scan_pixel(x: float, y: float, z: float, rho: float, W: int, H: int, tables=None):
+    """(column, row) of a scanner-frame direction in a W x H equirectangular scan."""
+    C, S, K = tables if tables is not None else scan_tables(W, H)
+    col, row = ctypes.c_int(), ctypes.c_int()
+    lib().or_scan_pixel(float(np.float32(x)), float(np.float32(y)), float(np.float32(z)), float(np.float32(rho)),
+                        W, H, C, S, K, ctypes.byref(col), ctypes.byref(row))
+    return col.value, row.value
 
 
 def vote_bin(scene, pyr_cam: np.ndarray, cam: int, i: int, j: int, k: int, num_bins=7, rule=0, delta=None,
@@ -188,12 +219,17 @@ def vote_bin(scene, pyr_cam: np.ndarray, cam: int, i: int, j: int, k: int, num_b
     cams, g = scene.cams, scene.grid
     bp = bins_params(g, num_bins, rule, delta, eta_over_delta)
     W, H = (int(v) for v in cams.wh[cam])
+    model = int(camera_models(cams)[cam])
+    tab = None
+    if model == 1:
+        tab = np.concatenate(scan_tables(W, H))
     return int(lib().or_vote_bin(np.ascontiguousarray(pyr_cam, dtype=np.float32), W, H,
                                  np.ascontiguousarray(cams.R[cam].reshape(-1), dtype=np.float32),
                                  np.ascontiguousarray(cams.t[cam], dtype=np.float32),
                                  np.ascontiguousarray(cams.intr[cam], dtype=np.float32),
                                  np.ascontiguousarray(g.origin, dtype=np.float32), float(g.h), i, j, k,
-                                 bp["delta"], bp["eta_over_delta"], bp["num_bins"], bp["rule"]))
+                                 bp["delta"], bp["eta_over_delta"], bp["num_bins"], bp["rule"], model,
+                                 None if tab is None else tab.ctypes.data))
 
 
 # ----------------------------------------------------------------------------

@@ -123,14 +123,80 @@ void or_pyramid(const float *depth, int W, int H, float *pyr)
     }
 }
 
+/* Boundary tables of an equirectangular 360-degree scan of W x H pixels
+ * (W a multiple of 4).  Column c covers the azimuths [2 pi c / W,
+ * 2 pi (c + 1) / W) measured in the scanner's x-y plane from +x towards
+ * +y; row r covers the polar angles [pi r / H, pi (r + 1) / H) measured
+ * from +z.  The boundary directions, rounded to binary32 from float64:
+ *   C[i] = cos(2 pi i / W), S[i] = sin(2 pi i / W)   for i in [0, W/4)
+ *   (the column boundaries of one quadrant; the others are these turned
+ *   by multiples of 90 degrees),
+ *   K[j] = cos(pi j / H)                              for j in [0, H). */
+void or_scan_tables(int W, int H, float *C, float *S, float *K)
+{
+    for (int i = 0; i < W / 4; i++) {
+        double a = (6.283185307179586 * (double)i) / (double)W;
+        C[i] = (float)cos(a);
+        S[i] = (float)sin(a);
+    }
+    for (int j = 0; j < H; j++) {
+        double a = (3.141592653589793 * (double)j) / (double)H;
+        K[j] = (float)cos(a);
+    }
+}
+
+/* Pixel of the direction (x, y, z) (scanner frame, binary32) of length
+ * rho in an equirectangular scan, decided by sign tests only:
+ *   quadrant q of (x, y): 0 if x > 0, y >= 0; 1 if x <= 0, y > 0;
+ *   2 if x < 0, y <= 0; 3 if x >= 0, y < 0 (the scanner's axis x = y = 0
+ *   counts as quadrant 0); (x', y') = (x, y) turned by -90 q degrees
+ *   (exact: swaps and negations), so x' >= 0 and y' >= 0;
+ *   column = q W/4 + the number of i in [1, W/4) with
+ *            fl(fl(C[i] y') - fl(S[i] x')) >= 0 (boundary i at or before
+ *            the direction);
+ *   row    = the number of j in [1, H) with z <= fl(K[j] rho) (boundary j
+ *            at or above the direction).
+ * Counted here by brute force over every boundary. */
+void or_scan_pixel(float x, float y, float z, float rho, int W, int H, const float *C, const float *S,
+                   const float *K, int *col, int *row)
+{
+    int q;
+    float xp, yp;
+    if (x > 0.0f && y >= 0.0f) { q = 0; xp = x; yp = y; }
+    else if (x <= 0.0f && y > 0.0f) { q = 1; xp = y; yp = -x; }
+    else if (x < 0.0f && y <= 0.0f) { q = 2; xp = -x; yp = -y; }
+    else if (x >= 0.0f && y < 0.0f) { q = 3; xp = -y; yp = x; }
+    else { q = 0; xp = x; yp = y; } /* x = y = 0 */
+    int c = 0;
+    for (int i = 1; i < W / 4; i++) {
+        float a = C[i] * yp;
+        float b = S[i] * xp;
+        if (a - b >= 0.0f) c++;
+    }
+    int r = 0;
+    for (int j = 1; j < H; j++) {
+        float k = K[j] * rho;
+        if (z <= k) r++;
+    }
+    *col = q * (W / 4) + c;
+    *row = r;
+}
+
 /* Bin of one (voxel, depth map) pair per Algorithm 1, or -1 for no vote.
  *   X = origin + (index + 1/2) h; Xc = R X + t (row by row, left to right);
- *   no vote if the camera depth z <= 0 or the projection leaves the image
- *   (Alg. 1: the map has no ray in that direction);
- *   the voxel's projected diameter s = h fx / z picks level
- *   l = floor(log2 s) (clamped to the pyramid), computed exactly by ilogbf;
- *   the pixel at level l is floor(px / 2^l), clamped to the level size;
- *   a = depth - z (depth maps hold camera-frame z, so "distance" is z);
+ *   model 0 (pinhole map of camera-frame z):
+ *     no vote if the camera depth z <= 0 or the projection leaves the image
+ *     (Alg. 1: the map has no ray in that direction); the voxel's distance
+ *     is z and its projected diameter s = h fx / z;
+ *   model 1 (equirectangular 360-degree scan of ranges; tab = its C, S, K
+ *     tables, see or_scan_tables):
+ *     the distance is the range rho = sqrt((x^2 + y^2) + z^2) of Xc (no
+ *     vote if 0), the pixel is or_scan_pixel's, and s = h fx / rho with fx
+ *     the map's pixels per radian;
+ *   s picks level l = floor(log2 s) (clamped to the pyramid), computed
+ *   exactly by ilogbf; the pixel at level l is floor(px / 2^l), clamped to
+ *   the level size;
+ *   a = depth - distance;
  *   no vote if the depth is invalid or a < -eta (occluded region);
  *   a is clamped to [-1, 1] after division by delta and binned:
  *     rule 0: nearest of nbins centres spread evenly over [-1, 1];
@@ -138,7 +204,7 @@ void or_pyramid(const float *depth, int W, int H, float *pyr)
  *             a = +1 folded into the last bin. */
 int or_vote_bin(const float *pyr, int W, int H, const float *R, const float *t, const float *intr,
                 const float *origin, float h, int i, int j, int k, float delta, float eta_over_delta,
-                int nbins, int rule)
+                int nbins, int rule, int model, const float *tab)
 {
     float X = origin[0] + ((float)i + 0.5f) * h;
     float Y = origin[1] + ((float)j + 0.5f) * h;
@@ -150,15 +216,30 @@ int or_vote_bin(const float *pyr, int W, int H, const float *R, const float *t, 
         acc = acc + R[3 * r + 2] * Z;
         xc[r] = acc + t[r];
     }
-    float z = xc[2];
-    if (!(z > 0.0f)) return -1;
     float fx = intr[0], fy = intr[1], cx = intr[2], cy = intr[3];
-    float px = fx * (xc[0] / z) + cx;
-    float py = fy * (xc[1] / z) + cy;
-    if (!(px >= 0.0f && px < (float)W && py >= 0.0f && py < (float)H)) return -1;
+    float dist, px, py;
+    if (model == 0) {
+        float z = xc[2];
+        if (!(z > 0.0f)) return -1;
+        px = fx * (xc[0] / z) + cx;
+        py = fy * (xc[1] / z) + cy;
+        if (!(px >= 0.0f && px < (float)W && py >= 0.0f && py < (float)H)) return -1;
+        dist = z;
+    } else {
+        float r2 = xc[0] * xc[0];
+        r2 = r2 + xc[1] * xc[1];
+        r2 = r2 + xc[2] * xc[2];
+        float rho = sqrtf(r2);
+        if (!(rho > 0.0f)) return -1;
+        int col, row;
+        or_scan_pixel(xc[0], xc[1], xc[2], rho, W, H, tab, tab + W / 4, tab + W / 2, &col, &row);
+        px = (float)col;
+        py = (float)row;
+        dist = rho;
+    }
 
     int L = or_pyr_levels(W, H);
-    float s = (h * fx) / z;
+    float s = (h * fx) / dist;
     int l = 0;
     if (s >= 1.0f) {
         l = ilogbf(s);
@@ -179,7 +260,7 @@ int or_vote_bin(const float *pyr, int W, int H, const float *R, const float *t, 
     float d = lev[(long)iy * w + ix];
     if (d == 0.0f) return -1;
 
-    float a = d - z;
+    float a = d - dist;
     float eta = eta_over_delta * delta;
     if (a < -eta) return -1;
     float an = fminf(1.0f, fmaxf(-1.0f, a / delta));
@@ -197,18 +278,27 @@ int or_vote_bin(const float *pyr, int W, int H, const float *R, const float *t, 
 
 /* Histograms of a list of voxels (all voxels when vox == NULL): every
  * depth map votes into each voxel per or_vote_bin, with its own weight
- * (1 for stereo depth maps, larger for near noise-free LIDAR, Alg. 1).
+ * (1 for stereo depth maps, larger for near noise-free LIDAR, Alg. 1),
+ * its own size wh and model (0 pinhole, 1 equirectangular scan).
  * pyrs holds the pyramids of all cameras back to back; hist is
  * [count][8] uint16, slots >= nbins stay 0.  Returns the largest total
  * vote seen in one voxel (so the caller can detect 16-bit overflow). */
 long or_histograms(const float *pyrs, int ncam, const float *R, const float *t, const float *intr,
-                   const int32_t *wh, const int32_t *vote, const float *origin, float h, int nx, int ny,
-                   int nz, float delta, float eta_over_delta, int nbins, int rule, const int64_t *vox,
-                   long nvox, uint16_t *hist)
+                   const int32_t *wh, const int32_t *vote, const int32_t *model, const float *origin, float h,
+                   int nx, int ny, int nz, float delta, float eta_over_delta, int nbins, int rule,
+                   const int64_t *vox, long nvox, uint16_t *hist)
 {
     long *off = (long *)malloc(sizeof(long) * (ncam + 1));
+    float **tab = (float **)calloc(ncam > 0 ? ncam : 1, sizeof(float *));
     off[0] = 0;
-    for (int c = 0; c < ncam; c++) off[c + 1] = off[c] + or_pyr_floats(wh[2 * c], wh[2 * c + 1]);
+    for (int c = 0; c < ncam; c++) {
+        off[c + 1] = off[c] + or_pyr_floats(wh[2 * c], wh[2 * c + 1]);
+        if (model[c] == 1) {
+            int W = wh[2 * c], H = wh[2 * c + 1];
+            tab[c] = (float *)malloc(sizeof(float) * (W / 2 + H));
+            or_scan_tables(W, H, tab[c], tab[c] + W / 4, tab[c] + W / 2);
+        }
+    }
     long count = vox ? nvox : (long)nx * ny * nz;
     long maxtot = 0;
 #pragma omp parallel for schedule(dynamic, 256) num_threads(g_threads) reduction(max : maxtot)
@@ -219,7 +309,7 @@ long or_histograms(const float *pyrs, int ncam, const float *R, const float *t, 
         long tot = 0;
         for (int c = 0; c < ncam; c++) {
             int b = or_vote_bin(pyrs + off[c], wh[2 * c], wh[2 * c + 1], R + 9 * c, t + 3 * c, intr + 4 * c,
-                                origin, h, i, j, k, delta, eta_over_delta, nbins, rule);
+                                origin, h, i, j, k, delta, eta_over_delta, nbins, rule, model[c], tab[c]);
             if (b >= 0) {
                 acc[b] += vote[c];
                 tot += vote[c];
@@ -228,6 +318,8 @@ long or_histograms(const float *pyrs, int ncam, const float *R, const float *t, 
         if (tot > maxtot) maxtot = tot;
         for (int b = 0; b < 8; b++) hist[8 * m + b] = (uint16_t)(acc[b] > 65535 ? 65535 : acc[b]);
     }
+    for (int c = 0; c < ncam; c++) free(tab[c]);
+    free(tab);
     free(off);
     return maxtot;
 }

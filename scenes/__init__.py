@@ -35,13 +35,20 @@ import numpy as np
 # ----------------------------------------------------------------------------
 @dataclasses.dataclass
 class Cameras:
-    """Pinhole cameras in structure-of-arrays form (all float32 / int32)."""
+    """Cameras in structure-of-arrays form (all float32 / int32): pinhole
+    depth maps (model 0) or equirectangular 360-degree scans (model 1)."""
 
     R: np.ndarray      # [n, 3, 3] float32, world -> camera rotation
     t: np.ndarray      # [n, 3] float32
-    intr: np.ndarray   # [n, 4] float32: fx, fy, cx, cy
+    intr: np.ndarray   # [n, 4] float32: fx, fy, cx, cy (a scan: fx = pixels per radian)
     wh: np.ndarray     # [n, 2] int32: width, height
     vote: np.ndarray   # [n] int32: vote weight (1, or 5 for LIDAR-like data)
+    model: np.ndarray = None  # [n] int32: 0 pinhole, 1 equirectangular scan (None: all pinhole)
+
+    def __post_init__(self):
+        if self.model is None:
+            self.model = np.zeros(int(self.R.shape[0]), dtype=np.int32)
+        self.model = np.asarray(self.model, dtype=np.int32)
 
     def __len__(self) -> int:
         return int(self.R.shape[0])
@@ -49,7 +56,7 @@ class Cameras:
     def subset(self, idx: Sequence[int]) -> "Cameras":
         idx = np.asarray(idx, dtype=np.int64)
         return Cameras(self.R[idx].copy(), self.t[idx].copy(), self.intr[idx].copy(),
-                       self.wh[idx].copy(), self.vote[idx].copy())
+                       self.wh[idx].copy(), self.vote[idx].copy(), self.model[idx].copy())
 
     def centers(self) -> np.ndarray:
         """Camera centres in world coordinates, float64: C = -R^T t."""
@@ -283,17 +290,29 @@ class HeightField:
 
 def heightfield_depth(cams: Cameras, k: int, hf: HeightField, bisect: int = 10, refine: int = 4,
                       device: str = "cpu") -> np.ndarray:
-    """Camera depth of the heightfield along each pixel ray.
-
-    Root of g(z) = (C + z d)_Z - H((C + z d)_XY) between the depths where
-    the ray enters and leaves the heightfield's Z range: `bisect` bisection
-    steps then `refine` Illinois (modified regula falsi) steps, in float64.
-    Where a ray crosses the surface more than once inside the bracket (rare
-    steep spots seen obliquely) the depth may belong to a later crossing;
-    0 where the ray never meets the height range."""
-    import torch
+    """Camera depth of the heightfield along each pixel ray of pinhole
+    camera k (0 where the ray never meets the height range); see
+    heightfield_hits."""
     C, d = pixel_rays(cams, k)
-    dt = torch.from_numpy(d.reshape(-1, 3)).to(device)
+    W, H = (int(v) for v in cams.wh[k])
+    return heightfield_hits(C, d.reshape(-1, 3), hf, bisect, refine, device).reshape(H, W)
+
+
+def heightfield_hits(C, dirs: np.ndarray, hf: HeightField, bisect: int = 10, refine: int = 4,
+                     device: str = "cpu") -> np.ndarray:
+    """Ray parameter s of the first hit C + s d with the heightfield for
+    each direction d of dirs [m, 3] (float64; with camera-z component 1, s
+    is the camera depth; with unit d, the range).
+
+    Root of g(s) = (C + s d)_Z - H((C + s d)_XY) between the parameters
+    where the ray enters and leaves the heightfield's Z range: `bisect`
+    bisection steps then `refine` Illinois (modified regula falsi) steps,
+    in float64.  Where a ray crosses the surface more than once inside the
+    bracket (rare steep spots seen obliquely) the hit may belong to a
+    later crossing; 0 where the ray never meets the height range (rays
+    that do not descend)."""
+    import torch
+    dt = torch.from_numpy(np.ascontiguousarray(dirs, dtype=np.float64)).to(device)
     Cx, Cy, Cz = (float(c) for c in C)
     dz = dt[:, 2]
     ok = dz < 0
@@ -333,8 +352,7 @@ def heightfield_depth(cams: Cameras, k: int, hf: HeightField, bisect: int = 10, 
         side = torch.where(above, torch.ones_like(side), -torch.ones_like(side))
     zc = torch.where(glo - ghi > 0, lo + (hi - lo) * (glo / torch.where(glo - ghi > 0, glo - ghi, torch.ones_like(glo))), 0.5 * (lo + hi))
     out = torch.where(ok, zc, torch.zeros_like(zc))
-    W, H = (int(v) for v in cams.wh[k])
-    return out.reshape(H, W).cpu().numpy()
+    return out.cpu().numpy()
 
 
 def terrain_scene(seed: int = 2, n: int = 256, n_side: int = 8, W: int = 1024, H: int = 1024,
@@ -660,7 +678,8 @@ def scan_cameras(center, W: int = 256, vote: int = 5) -> Cameras:
 
 def concat_cameras(a: Cameras, b: Cameras) -> Cameras:
     return Cameras(np.concatenate([a.R, b.R]), np.concatenate([a.t, b.t]), np.concatenate([a.intr, b.intr]),
-                   np.concatenate([a.wh, b.wh]), np.concatenate([a.vote, b.vote]))
+                   np.concatenate([a.wh, b.wh]), np.concatenate([a.vote, b.vote]),
+                   np.concatenate([a.model, b.model]))
 
 
 def terrain_scans(seed: int = 2, positions=((0.25, 0.25), (0.75, 0.25), (0.25, 0.75), (0.75, 0.75)),
@@ -700,3 +719,89 @@ def scan_sphere_scene(center=(2.2, 0.4, 0.3), W: int = 128, n: int = 32, extent:
     rng = np.random.default_rng(seed)
     d_scan = add_noise(clean, scan, grid, sigma, 0.0, rng)
     return Scene(d_scan, scan, grid, name="scan-sphere")
+
+
+# ----------------------------------------------------------------------------
+# 360-degree scans (terrestrial LIDAR, Sec. 3.1) as equirectangular range maps
+# ----------------------------------------------------------------------------
+def scan360_cameras(centers, W: int = 2048, H: int = 1024, vote: int = 5) -> Cameras:
+    """Equirectangular 360-degree scanners at `centers` (world, float64),
+    their frames aligned with the world's (R = I, t = -C): column c covers
+    azimuths [2 pi c / W, 2 pi (c + 1) / W) from +x towards +y, row r polar
+    angles [pi r / H, pi (r + 1) / H) from +z; fx = W / (2 pi) pixels per
+    radian; each map holds the range along its pixel rays (model 1)."""
+    cs = np.asarray(centers, dtype=np.float64).reshape(-1, 3)
+    Rs = [np.eye(3) for _ in cs]
+    ts = [-c for c in cs]
+    cams = make_cameras(Rs, ts, W / (2.0 * math.pi), W / (2.0 * math.pi), 0.0, 0.0, W, H, vote=vote)
+    cams.model[:] = 1
+    return cams
+
+
+def scan360_rays(cams: Cameras, k: int):
+    """Scanner centre (world, float64) and the unit direction (world) of
+    every pixel centre of equirectangular scan k, [H, W, 3]."""
+    W, H = (int(v) for v in cams.wh[k])
+    phi = 2.0 * math.pi * (np.arange(W, dtype=np.float64) + 0.5) / W
+    theta = math.pi * (np.arange(H, dtype=np.float64) + 0.5) / H
+    ds = np.empty((H, W, 3), dtype=np.float64)
+    ds[..., 0] = np.sin(theta)[:, None] * np.cos(phi)[None, :]
+    ds[..., 1] = np.sin(theta)[:, None] * np.sin(phi)[None, :]
+    ds[..., 2] = np.cos(theta)[:, None]
+    R = cams.R[k].astype(np.float64)
+    return cams.centers()[k], ds @ R  # scanner frame -> world: R^T d
+
+
+def sphere_range(cams: Cameras, k: int, radius: float = 1.0, center=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Exact range (float64) from scanner k to a sphere along its pixel
+    rays (first hit in front of the scanner, also from inside), 0 on a miss."""
+    C, d = scan360_rays(cams, k)
+    oc = C - np.asarray(center, dtype=np.float64)
+    b = d @ oc
+    c = float(oc @ oc) - radius * radius
+    disc = b * b - c
+    hit = disc >= 0
+    root = np.sqrt(np.where(hit, disc, 0.0))
+    s0, s1 = -b - root, -b + root
+    s = np.where(s0 > 0, s0, s1)
+    return np.where(hit & (s > 0), s, 0.0)
+
+
+def terrain_scans360(seed: int = 2, positions=((0.25, 0.25), (0.75, 0.25), (0.25, 0.75), (0.75, 0.75)),
+                     height: float = 0.03, W: int = 4096, H: int = 2048, lattice: int = 2048, hurst: float = 0.8,
+                     amplitude: float = 0.2, sigma_vox: float = 0.05, n: int = 256, device: str = "cpu"):
+    """Terrestrial 360-degree scans of the terrain of terrain_scene (same
+    seed, same heightfield) at their own resolution: one equirectangular
+    W x H scanner `height` above the ground at each (x, y) position (vote
+    5), the range along every pixel ray that descends onto the terrain (0
+    elsewhere), N(0, (sigma_vox h)^2) noise on the range and no outliers.
+    Returns (range maps [k, H, W] float32, cams)."""
+    z01 = fbm_heightfield(lattice, hurst, seed)
+    hf = HeightField(z01, base=0.5, amplitude=amplitude)
+    centers = [np.array([x, y, float(hf([x], [y])[0]) + height]) for (x, y) in positions]
+    cams = scan360_cameras(centers, W, H)
+    rng = np.random.default_rng(seed + 3000)
+    h = float(np.float32(1.0 / n))
+    out = np.zeros((len(cams), H, W), dtype=np.float32)
+    for k in range(len(cams)):
+        C, d = scan360_rays(cams, k)
+        r = heightfield_hits(C, d.reshape(-1, 3), hf, device=device).reshape(H, W)
+        valid = r > 0
+        r = r + rng.normal(0.0, sigma_vox * h, size=r.shape)
+        out[k] = np.where(valid & (r > 0), r, 0.0).astype(np.float32)
+    return out, cams
+
+
+def scan360_sphere_scene(center=(2.2, 0.4, 0.3), W: int = 512, H: int = 256, n: int = 32, extent: float = 1.5,
+                         seed: int = 12, sigma: float = 0.001) -> Scene:
+    """The unit sphere seen by one equirectangular 360-degree scanner
+    (vote 5, low range noise, no outliers) on the block of sphere_scene."""
+    cams = scan360_cameras([center], W, H)
+    h = np.float32(2.0 * extent / n)
+    grid = Grid(np.full(3, -extent, dtype=np.float32), float(h), (n, n, n), 0)
+    r = sphere_range(cams, 0)
+    rng = np.random.default_rng(seed)
+    valid = r > 0
+    r = r + rng.normal(0.0, sigma, size=r.shape)
+    depth = np.where(valid & (r > 0), r, 0.0).astype(np.float32)[None]
+    return Scene(depth, cams, grid, name="scan360-sphere")

@@ -247,3 +247,134 @@ def test_terrain_scan_generator_geometry():
     assert (d[up[0]] == 0).all()
     assert (d[down[0]] > 0).all()
     assert abs(float(d[down[0]][16, 16]) - 0.03) < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# 360-degree scans (Sec. 3.1: terrestrial LIDAR as 360-degree depth maps,
+# vote 5 in Algorithm 1) as equirectangular range maps
+# ---------------------------------------------------------------------------
+def test_scan_pixel_of_axis_directions():
+    """The axis directions land on the quadrant and equator boundaries:
+    +x column 0, +y W/4, -x W/2, -y 3W/4 (all on row H/2, the equator's
+    row); +z row 0 and -z row H-1."""
+    W, H = 64, 32
+    tab = oracle.scan_tables(W, H)
+    assert oracle.scan_pixel(1, 0, 0, 1, W, H, tab) == (0, H // 2)
+    assert oracle.scan_pixel(0, 1, 0, 1, W, H, tab) == (W // 4, H // 2)
+    assert oracle.scan_pixel(-1, 0, 0, 1, W, H, tab) == (W // 2, H // 2)
+    assert oracle.scan_pixel(0, -1, 0, 1, W, H, tab) == (3 * W // 4, H // 2)
+    assert oracle.scan_pixel(0, 0, 1, 1, W, H, tab)[1] == 0
+    assert oracle.scan_pixel(0, 0, -1, 1, W, H, tab)[1] == H - 1
+    C, S, K = tab
+    assert C[0] == 1.0 and S[0] == 0.0 and K[0] == 1.0
+    assert (np.diff(C) <= 0).all() and (np.diff(S) >= 0).all() and (np.diff(K) <= 0).all()
+    # a direction exactly on a boundary belongs to the pixel that boundary
+    # opens (pixels are half-open): column i for (C_i, S_i) in every
+    # quadrant, row j where z equals K_j times the range exactly
+    for i in (1, 5, W // 4 - 1):
+        for q, (x, y) in enumerate([(C[i], S[i]), (-S[i], C[i]), (-C[i], -S[i]), (S[i], -C[i])]):
+            assert oracle.scan_pixel(x, y, 0.0, 1.0, W, H, tab)[0] == q * W // 4 + i, (i, q)
+    on_row = 0
+    for j in range(1, H):
+        z = np.float32(K[j])
+        x = np.float32(np.sqrt(max(0.0, 1.0 - float(z) * float(z))))
+        rho = np.float32(np.sqrt(np.float32(np.float32(x * x) + np.float32(z * z))))
+        if rho == np.float32(1.0):
+            assert oracle.scan_pixel(x, 0.0, z, rho, W, H, tab)[1] == j, j
+            on_row += 1
+    assert on_row >= 3
+
+
+@pytest.mark.parametrize("W,H", [(64, 32), (2048, 1024), (12, 5)])
+def test_scan_pixel_matches_float64_angles(W, H):
+    """Away from a pixel boundary, the sign-test pixel equals the textbook
+    equirectangular pixel floor(phi W / 2 pi), floor(theta H / pi) with phi =
+    atan2(y, x) in [0, 2 pi) and theta = acos(z / |d|) taken in float64."""
+    rng = np.random.default_rng(W + H)
+    d = rng.normal(size=(4000, 3)).astype(np.float32)
+    d[:200, 2] = 0.0  # on the equator
+    d[200:300, :2] *= 1e-3  # near the poles
+    tab = oracle.scan_tables(W, H)
+    checked = 0
+    for x, y, z in d:
+        x64, y64, z64 = float(x), float(y), float(z)
+        rho32 = np.float32(np.sqrt(np.float32(np.float32(x * x) + np.float32(y * y)) + np.float32(z * z)))
+        phi = np.arctan2(y64, x64) % (2 * np.pi)
+        theta = np.arccos(z64 / np.sqrt(x64 * x64 + y64 * y64 + z64 * z64))
+        fc, fr = phi * W / (2 * np.pi), theta * H / np.pi
+        if min(fc % 1.0, 1 - fc % 1.0) < 1e-3 or min(fr % 1.0, 1 - fr % 1.0) < 1e-3:
+            continue
+        col, row = oracle.scan_pixel(x, y, z, rho32, W, H, tab)
+        assert (col, row) == (int(fc) % W, int(fr)), (x, y, z)
+        checked += 1
+    assert checked > 3000
+
+
+def _scanner_in_sphere(m=16, n=61, W=64, H=32):
+    """A scanner at the centre voxel of an n^3 block (h = 1/16) inside a
+    sphere of radius m h centred on it: a noise-free constant range map."""
+    h = 1.0 / 16
+    c = n // 2
+    origin = np.full(3, -(c + 0.5) * h, dtype=np.float32)
+    cams = scenes.scan360_cameras([(0.0, 0.0, 0.0)], W, H)
+    depth = np.full((1, H, W), np.float32(m * h), dtype=np.float32)
+    return scenes.Scene(depth, cams, scenes.Grid(origin, h, (n, n, n), 0)), c
+
+
+def test_scan_inside_sphere_bins_by_range_golden():
+    """Voxels on the six axes through the scanner lie at range k h exactly;
+    with the surface at range m h they are d = m - k voxels in front of it
+    and bin as the fronto-parallel plane's golden table says (the scan's
+    distance is the range, the same delta = 3 voxels and eta = 9)."""
+    m = 16
+    sc, c = _scanner_in_sphere(m)
+    n = sc.grid.n[0]
+    hist, _ = oracle.histograms(sc)
+    Hh = hist.reshape(n, n, n, 8)
+    table = {d: b0 for d, b0, _ in _plane_table()}
+    seen = 0
+    for axis in range(3):
+        for sign in (1, -1):
+            for k in range(1, c + 1):
+                idx = [c, c, c]
+                idx[axis] += sign * k
+                row = Hh[idx[2], idx[1], idx[0]]
+                d = m - k
+                if d not in table:
+                    continue
+                expected = table[d]
+                if expected is None:
+                    assert row.sum() == 0, (axis, sign, k, row)
+                else:
+                    assert row[expected] == 5 and row.sum() == 5, (axis, sign, k, row)
+                seen += 1
+    assert seen == 6 * 13
+    assert Hh[c, c, c].sum() == 0  # the scanner's own voxel has no direction
+
+
+def test_mixed_sizes_and_models_add_up():
+    """Pinhole maps of 128^2 and a 512 x 256 scan in one histogram call
+    equal the sum of their separate calls (each camera reads its own
+    pyramid at its own size)."""
+    ring = scenes.sphere_scene(n=24)
+    scan = scenes.scan360_sphere_scene(n=24)
+    cams = scenes.concat_cameras(scan.cams, ring.cams)
+    pyr = np.concatenate([oracle.pyramids(scan.depth), oracle.pyramids(ring.depth)])
+    both, _ = oracle.histograms(scenes.Scene(None, cams, ring.grid), pyr)
+    a, _ = oracle.histograms(scenes.Scene(ring.depth, ring.cams, ring.grid))
+    b, _ = oracle.histograms(scenes.Scene(scan.depth, scan.cams, ring.grid))
+    assert b.sum() > 0 and a.sum() > 0
+    assert np.array_equal(both.astype(np.int64), a.astype(np.int64) + b.astype(np.int64))
+
+
+def test_scan360_generator_geometry():
+    """A scanner at a sphere's centre sees the radius in every pixel; a
+    terrain scanner sees the ground `height` below it straight down and
+    nothing above the horizon."""
+    cams = scenes.scan360_cameras([(0.1, -0.2, 0.3)], 16, 8)
+    r = scenes.sphere_range(cams, 0, radius=2.0, center=(0.1, -0.2, 0.3))
+    np.testing.assert_allclose(r, 2.0, rtol=1e-7)  # the centre is kept in float32
+    d, tc = scenes.terrain_scans360(positions=((0.4, 0.6),), W=64, H=32, n=32, sigma_vox=0.0)
+    assert d.shape == (1, 32, 64) and list(tc.model) == [1] and list(tc.vote) == [5]
+    assert (d[0, : 32 // 2 - 1] == 0).all()  # rows above the horizon
+    assert abs(float(d[0, -1].mean()) - 0.03) < 2e-3  # the row around -z
