@@ -28,10 +28,11 @@
  *     tile tables of tgv_solve_batch, the state of a tgv_solve without one)
  *     waits on the device for the previous call's use of it.  Caller-owned
  *     arrays and states used on several streams are ordered by the caller.
- *   - Depth maps hold the camera-frame z of the surface seen through each
- *     pixel; values that are not finite or <= 0 mean "no sample".
- *   - Camera model: Xc = R X + t (R row-major); pixel column i covers
- *     [i, i+1); px = fx Xc/Zc + cx, py = fy Yc/Zc + cy.
+ *   - Depth maps hold the camera-frame z (pinhole maps) or the range (360-
+ *     degree scans) of the surface seen through each pixel; values that are
+ *     not finite or <= 0 mean "no sample".
+ *   - Camera models: see tgv_camera (pinhole depth maps of camera-frame z,
+ *     equirectangular 360-degree scans of ranges).
  */
 #ifndef TGV_H
 #define TGV_H
@@ -52,16 +53,42 @@ typedef enum {
     TGV_E_UNSUPPORTED = 5  /* valid request this build does not implement */
 } tgv_status;
 
-/* One pinhole camera (80 bytes). vote: weight of its votes (1 for stereo
- * depth maps, 5 for near noise-free LIDAR scans, Algorithm 1). */
+/* One camera (80 bytes): a depth map seen through a pinhole or a 360-degree
+ * scan.  vote: weight of its votes (1 for stereo depth maps, 5 for near
+ * noise-free LIDAR scans, Algorithm 1).  model:
+ *   TGV_MODEL_PINHOLE: Xc = R X + t (R row-major); the map holds camera-frame
+ *     z; pixel column i covers [i, i+1) of px = fx Xc/Zc + cx, row j of
+ *     py = fy Yc/Zc + cy; width x height pixels.
+ *   TGV_MODEL_SCAN360: an equirectangular 360-degree scan (terrestrial
+ *     LIDAR, Sec. 3.1) of width x height pixels (width divisible by 4)
+ *     holding ranges (distances from the scanner's centre).  Xc = R X + t
+ *     is the direction in the scanner's frame; column c covers azimuths
+ *     [2 pi c / width, 2 pi (c + 1) / width) from +x towards +y, row r polar
+ *     angles [pi r / height, pi (r + 1) / height) from +z; fx is the map's
+ *     pixels per radian (width / (2 pi)), which with the range sets the
+ *     pyramid level; fy, cx, cy are unused.  The pixel is decided by sign
+ *     tests against tables of the boundary directions: C[i] = cos(2 pi i /
+ *     width), S[i] = sin(2 pi i / width) (i < width / 4) and K[j] = cos(pi j
+ *     / height) (j < height), each evaluated in double as written
+ *     ((6.283185307179586 i) / width, (3.141592653589793 j) / height) and
+ *     rounded to float.  The direction is turned by a multiple of -90
+ *     degrees into the first quadrant (quadrant 0: x > 0, y >= 0; 1: x <= 0,
+ *     y > 0; 2: x < 0, y <= 0; 3: x >= 0, y < 0; the axis x = y = 0 counts
+ *     as quadrant 0) giving (x', y'); the column is quadrant * width / 4
+ *     plus the number of i in [1, width / 4) with C[i] y' - S[i] x' >= 0,
+ *     the row the number of j in [1, height) with z <= K[j] rho, where rho
+ *     = sqrt((x^2 + y^2) + z^2) is the voxel's range (every operation
+ *     rounded to float on its own). */
 typedef struct {
     float R[9];
     float t[3];
     float fx, fy, cx, cy;
     int32_t width, height;
     int32_t vote;
-    int32_t reserved;
+    int32_t model;  /* TGV_MODEL_* */
 } tgv_camera;
+
+enum { TGV_MODEL_PINHOLE = 0, TGV_MODEL_SCAN360 = 1 };
 
 /* A regular voxel block: voxel (i, j, k) has centre origin + (idx + 1/2) h.
  * Voxels closer than `halo` cells to a face keep u frozen during a solve
@@ -174,25 +201,45 @@ tgv_status tgv_build_pyramids(tgv_ctx *ctx, const float *depth, int32_t n_cams, 
 /* ---- histograms (Sec. 3.4, Algorithm 1) ------------------------------ */
 
 /* Conservative camera cull for a block (host only): writes to keep_host the
- * indices of the cameras whose view frustum may contain a voxel centre of
- * the block, returns their count (or -1 on bad arguments).  Culling never
- * changes a histogram: dropped cameras cast no vote. */
+ * indices of the cameras whose view may contain a voxel centre of the
+ * block (a pinhole camera: its frustum; a 360-degree scan: always), returns
+ * their count (or -1 on bad arguments).  Culling never changes a
+ * histogram: dropped cameras cast no vote. */
 int32_t tgv_cull_cameras(const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid, int32_t *keep_host);
 
 /* Vote histograms of every voxel of `grid` from n_cams cameras whose
  * pyramids are packed in pyr (as written by tgv_build_pyramids, all
  * cameras width W and height H).  Output hist[nz][ny][nx][8] uint16: slot
  * k < num_bins counts the votes of bin k, slots >= num_bins are 0.  Per
- * (voxel, camera): project the voxel centre; no vote if behind the camera,
- * outside the image, on an invalid sample or further than eta behind the
- * observed surface; else bin clamp((depth - z) / delta, -1, 1) by `rule`.
- * The level read is floor(log2(h fx / z)), clamped to the pyramid.  All
+ * (voxel, camera): project the voxel centre (pinhole) or find its pixel
+ * and range (scan); no vote if behind a pinhole camera, outside its image,
+ * on an invalid sample or further than eta behind the observed surface;
+ * else bin clamp((depth - distance) / delta, -1, 1) by `rule`, where the
+ * distance is the camera-frame z (pinhole) or the range (scan).  The level
+ * read is floor(log2(h fx / distance)), clamped to the pyramid.  All
  * arithmetic is IEEE binary32 without contraction, so counts are exact and
  * reproducible.  TGV_E_OVERFLOW if the votes of the cameras kept by the
  * cull could sum past 65535. */
 tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32_t W, int32_t H, const tgv_camera *cams_host,
                                 int32_t n_cams, const tgv_grid *grid, const tgv_bins *bins, uint16_t *hist,
                                 void *stream);
+
+/* flags of tgv_build_histograms_ex */
+enum { TGV_HIST_ACCUMULATE = 1 };
+
+/* tgv_build_histograms for cameras of different sizes and models (stereo
+ * depth maps and 360-degree scans at their own resolutions, fused into one
+ * block, Sec. 3.1): camera c is cams_host[c].width x cams_host[c].height
+ * and its pyramid (as tgv_build_pyramids writes it at that size) starts at
+ * pyr + pyr_offsets_host[c] floats.  flags 0 overwrites hist; with
+ * TGV_HIST_ACCUMULATE the votes are added to the counts hist already holds,
+ * of which every voxel has at most prior_votes (e.g. the summed votes of
+ * earlier calls); TGV_E_OVERFLOW if prior_votes plus the votes of the kept
+ * cameras could exceed 65535.  prior_votes must be 0 without the flag. */
+tgv_status tgv_build_histograms_ex(tgv_ctx *ctx, const float *pyr, const int64_t *pyr_offsets_host,
+                                   const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid,
+                                   const tgv_bins *bins, int32_t flags, int32_t prior_votes, uint16_t *hist,
+                                   void *stream);
 
 /* ---- solver (Eq. 2, Sec. 3.2, Sec. 4.5) ----------------------------- */
 
@@ -297,6 +344,17 @@ tgv_status tgv_extract_crossings(tgv_ctx *ctx, const tgv_grid *grid, const float
 /* Energy statistics of a state (synchronises the stream). */
 tgv_status tgv_energy(tgv_ctx *ctx, const tgv_state *st, const uint16_t *hist, const tgv_bins *bins,
                       const tgv_params *params, tgv_stats *stats_host, void *stream);
+
+/* ---- measurement ------------------------------------------------------ */
+
+/* Copy `bytes` (a multiple of 16; both pointers 16-byte aligned) from src
+ * to dst with a plain streaming kernel: every byte read once and written
+ * once, the pass the solver kernels' memory rates are measured against.
+ * variant selects its shape: bits 0-1 the 16-byte vectors per lane and
+ * trip (1, 2, 4, 8), bit 2 non-temporal loads and stores, bits 3-4 the
+ * workgroups of 256 lanes per compute unit (2, 4, 8, 16); 0 <= variant <
+ * 32.  The buffers must not overlap. */
+tgv_status tgv_stream_copy(tgv_ctx *ctx, const void *src, void *dst, int64_t bytes, int32_t variant, void *stream);
 
 #ifdef __cplusplus
 }

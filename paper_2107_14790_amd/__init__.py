@@ -25,6 +25,8 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF, SCHED_FUSED2, SCHED_AUTO = 0, 1, 2, 3, 4
 FLAG_GRAPH = 1
 FLAG_TVL1 = 2
+MODEL_PINHOLE, MODEL_SCAN360 = 0, 1
+HIST_ACCUMULATE = 1
 STORAGE_NAMES = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
 
 
@@ -41,7 +43,7 @@ class Camera(ctypes.Structure):
     _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
                 ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("vote", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("model", ctypes.c_int32)]
 
 
 class GridT(ctypes.Structure):
@@ -81,6 +83,9 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_int32)]),
     "tgv_build_histograms": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Camera),
                                             ctypes.c_int32, ctypes.POINTER(GridT), ctypes.POINTER(BinsT), _vp, _vp]),
+    "tgv_build_histograms_ex": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(Camera),
+                                               ctypes.c_int32, ctypes.POINTER(GridT), ctypes.POINTER(BinsT),
+                                               ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
     "tgv_state_create": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), ctypes.c_int32, ctypes.POINTER(_vp)]),
     "tgv_state_destroy": (None, [_vp]),
     "tgv_state_wrap": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), ctypes.c_int32, _vp, ctypes.c_int64,
@@ -95,6 +100,7 @@ _SIGS = {
                                   ctypes.POINTER(StatsT), _vp]),
     "tgv_extract_crossings": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, _vp, ctypes.c_int64,
                                              ctypes.POINTER(ctypes.c_int64), _vp]),
+    "tgv_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]),
     "tgv_prolongate": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, ctypes.POINTER(GridT), _vp, _vp]),
     "tgv_solve_coarse_to_fine": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Camera),
                                                 ctypes.c_int32, ctypes.POINTER(GridT), ctypes.POINTER(BinsT),
@@ -218,8 +224,9 @@ def grid_from(obj) -> GridT:
     return grid_c(obj.origin, obj.h, obj.n, getattr(obj, "halo", 0))
 
 
-def cameras_c(R, t, intr, wh, vote):
+def cameras_c(R, t, intr, wh, vote, model=None):
     n = int(np.asarray(R).shape[0])
+    model = np.zeros(n, dtype=np.int32) if model is None else np.asarray(model, dtype=np.int32).reshape(n)
     arr = (Camera * max(n, 1))()
     R = np.asarray(R, dtype=np.float32).reshape(n, 9)
     t = np.asarray(t, dtype=np.float32).reshape(n, 3)
@@ -235,15 +242,16 @@ def cameras_c(R, t, intr, wh, vote):
         c.fx, c.fy, c.cx, c.cy = (float(v) for v in intr[k])
         c.width, c.height = int(wh[k, 0]), int(wh[k, 1])
         c.vote = int(vote[k])
-        c.reserved = 0
+        c.model = int(model[k])
     return arr, n
 
 
 def cameras_from(obj):
-    """Accepts (array, n) or an object with R, t, intr, wh, vote arrays."""
+    """Accepts (array, n) or an object with R, t, intr, wh, vote (and
+    optionally model) arrays."""
     if isinstance(obj, tuple):
         return obj
-    return cameras_c(obj.R, obj.t, obj.intr, obj.wh, obj.vote)
+    return cameras_c(obj.R, obj.t, obj.intr, obj.wh, obj.vote, getattr(obj, "model", None))
 
 
 def stats_dict(s: StatsT) -> dict:
@@ -321,6 +329,45 @@ class Context:
             out = torch.empty((nvox, 8), dtype=torch.int16, device=pyr.device)
         self._check(self.lib.tgv_build_histograms(self.h, _ptr(pyr), W, H, arr, n, ctypes.byref(g), ctypes.byref(b),
                                                   _ptr(out), _stream(stream)))
+        return out
+
+    def build_pyramids_mixed(self, depths, stream=None):
+        """Pyramids of several stacks of depth maps of different sizes (a list
+        of float32 tensors [n_i, H_i, W_i]) packed into one buffer: returns
+        (pyr, offsets), offsets[c] the float offset of camera c's pyramid, in
+        the order of the stacks."""
+        sizes = [(int(d.shape[0]), int(d.shape[2]), int(d.shape[1])) for d in depths]
+        total = sum(n * self.pyramid_floats(W, H) for n, W, H in sizes)
+        dev = depths[0].device
+        pyr = torch.empty(total, dtype=torch.float32, device=dev)
+        offsets, at = [], 0
+        for d, (n, W, H) in zip(depths, sizes):
+            per = self.pyramid_floats(W, H)
+            self.build_pyramids(d, out=pyr[at:at + n * per].view(n, per), stream=stream)
+            offsets.extend(at + k * per for k in range(n))
+            at += n * per
+        return pyr, np.asarray(offsets, dtype=np.int64)
+
+    def build_histograms_ex(self, pyr: torch.Tensor, offsets, cams, grid, bins: Bins = None, accumulate: bool = False,
+                            prior_votes: int = 0, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """Histograms from cameras of different sizes and models (pinhole maps
+        and 360-degree scans), camera c's pyramid at pyr[offsets[c]:]; with
+        accumulate, added to out's counts (at most prior_votes per voxel)."""
+        g = grid_from(grid)
+        b = (bins or Bins()).to_c(g.h)
+        arr, n = cameras_from(cams)
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        if offs.size != n:
+            raise ValueError("one pyramid offset per camera")
+        nvox = g.nx * g.ny * g.nz
+        if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs the histograms to add to")
+            out = torch.empty((nvox, 8), dtype=torch.int16, device=pyr.device)
+        optr = offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        self._check(self.lib.tgv_build_histograms_ex(self.h, _ptr(pyr), optr, arr, n, ctypes.byref(g), ctypes.byref(b),
+                                                     HIST_ACCUMULATE if accumulate else 0, int(prior_votes),
+                                                     _ptr(out), _stream(stream)))
         return out
 
     # -- solver ------------------------------------------------------------
@@ -403,6 +450,15 @@ class Context:
         self._check(self.lib.tgv_extract_crossings(self.h, ctypes.byref(g), _ptr(u), _ptr(out), cnt.value,
                                                    ctypes.byref(cnt), _stream(stream)))
         return out[:cnt.value]
+
+    def stream_copy(self, src: torch.Tensor, dst: torch.Tensor, variant: int = 0, stream=None):
+        """Plain streaming copy of src into dst (same byte size, a multiple of
+        16) by the library's copy kernel of the given shape (see
+        tgv_stream_copy)."""
+        nbytes = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != nbytes:
+            raise ValueError("src and dst differ in size")
+        self._check(self.lib.tgv_stream_copy(self.h, _ptr(src), _ptr(dst), nbytes, int(variant), _stream(stream)))
 
     def energy(self, state: "State", hist: torch.Tensor, params: Params = None, bins: Bins = None,
                stream=None) -> dict:

@@ -247,6 +247,10 @@ extern "C" int32_t tgv_cull_cameras(const tgv_camera *cams, int32_t n_cams, cons
     int cnt = 0;
     for (int c = 0; c < n_cams; c++) {
         const tgv_camera &cm = cams[c];
+        if (cm.model != TGV_MODEL_PINHOLE) {  // a 360-degree scan sees every direction
+            keep[cnt++] = c;
+            continue;
+        }
         double zmin = INFINITY, pxmin = INFINITY, pxmax = -INFINITY, pymin = INFINITY, pymax = -INFINITY;
         bool all_front = true;
         for (int k = 0; k < 8; k++) {
@@ -289,45 +293,84 @@ extern "C" int32_t tgv_cull_cameras(const tgv_camera *cams, int32_t n_cams, cons
     return cnt;
 }
 
-extern "C" tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32_t W, int32_t H,
-                                           const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid,
-                                           const tgv_bins *bins, uint16_t *hist, void *stream) {
-    if (!ctx) return TGV_E_INVAL;
-    if (!pyr || !hist || !cams_host || n_cams < 0 || W < 1 || H < 1)
-        return fail(ctx, TGV_E_INVAL, "tgv_build_histograms: bad arguments");
-    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_build_histograms: bad grid");
-    if (!bins_ok(bins)) return fail(ctx, TGV_E_INVAL, "tgv_build_histograms: bad bins");
+// Histograms of `grid` from n_cams cameras, camera c's pyramid at pyr +
+// offs[c] floats (each at the camera's own size), the counts added to
+// hist's when `accumulate` (whose voxels hold at most `prior` votes).
+static tgv_status histograms_impl(tgv_ctx *ctx, const char *who, const float *pyr, const int64_t *offs,
+                                  const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid,
+                                  const tgv_bins *bins, bool accumulate, int32_t prior, uint16_t *hist,
+                                  void *stream) {
+    if (!pyr || !hist || !cams_host || n_cams < 0 || prior < 0 || (!accumulate && prior != 0))
+        return fail(ctx, TGV_E_INVAL, "%s: bad arguments", who);
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "%s: bad grid", who);
+    if (!bins_ok(bins)) return fail(ctx, TGV_E_INVAL, "%s: bad bins", who);
     for (int c = 0; c < n_cams; c++) {
-        if (cams_host[c].width != W || cams_host[c].height != H)
-            return fail(ctx, TGV_E_INVAL, "camera %d is %dx%d, pyramids are %dx%d", c, cams_host[c].width,
-                        cams_host[c].height, W, H);
-        if (cams_host[c].vote < 0 || cams_host[c].vote > 65535)
-            return fail(ctx, TGV_E_INVAL, "camera %d has vote %d", c, cams_host[c].vote);
+        const tgv_camera &cm = cams_host[c];
+        if (cm.width < 1 || cm.height < 1) return fail(ctx, TGV_E_INVAL, "%s: camera %d is %dx%d", who, c, cm.width, cm.height);
+        if (cm.vote < 0 || cm.vote > 65535) return fail(ctx, TGV_E_INVAL, "%s: camera %d has vote %d", who, c, cm.vote);
+        if (cm.model != TGV_MODEL_PINHOLE && cm.model != TGV_MODEL_SCAN360)
+            return fail(ctx, TGV_E_INVAL, "%s: camera %d has model %d", who, c, cm.model);
+        if (cm.model == TGV_MODEL_SCAN360 && (cm.width % 4 != 0 || !(cm.fx > 0.0f) || !isfinite(cm.fx)))
+            return fail(ctx, TGV_E_INVAL, "%s: scan %d needs a width divisible by 4 and fx > 0", who, c);
+        const PyrGeom g = pyr_geom(cm.width, cm.height);
+        if (g.L > 24 || g.cam_stride >= (1LL << 31))
+            return fail(ctx, TGV_E_INVAL, "%s: camera %d's image is too large", who, c);
+        if (offs[c] < 0) return fail(ctx, TGV_E_INVAL, "%s: camera %d's pyramid offset is negative", who, c);
     }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     std::vector<int32_t> keep(n_cams > 0 ? n_cams : 1);
     int nk = tgv_cull_cameras(cams_host, n_cams, grid, keep.data());
-    long long total = 0;
+    long long total = prior;
     for (int k = 0; k < nk; k++) total += cams_host[keep[k]].vote;
     if (total > 65535)
-        return fail(ctx, TGV_E_OVERFLOW, "votes of %d cameras sum to %lld > 65535", nk, total);
-    // stage the culled camera table (wait until the previous upload left the staging buffer)
+        return fail(ctx, TGV_E_OVERFLOW, "%s: %d votes already possible plus those of %d cameras sum to %lld > 65535",
+                    who, prior, nk, total);
+    // boundary tables of the kept scans, one set per distinct size
+    std::vector<std::pair<long long, int>> tab_of;  // (W << 32 | H, float offset)
+    std::vector<int> cam_tab(nk, 0);
+    long long tab_floats = 0;
+    for (int k = 0; k < nk; k++) {
+        const tgv_camera &c = cams_host[keep[k]];
+        if (c.model != TGV_MODEL_SCAN360) continue;
+        const long long key = ((long long)c.width << 32) | c.height;
+        int at = -1;
+        for (auto &e : tab_of)
+            if (e.first == key) at = e.second;
+        if (at < 0) {
+            at = (int)tab_floats;
+            tab_of.push_back({key, at});
+            tab_floats += c.width / 2 + c.height;
+        }
+        cam_tab[k] = at;
+    }
+    if (tab_floats >= (1LL << 31)) return fail(ctx, TGV_E_INVAL, "%s: scan tables too large", who);
+    // stage the culled camera table and the scan tables (wait until the
+    // previous upload left the staging buffer)
+    const long long cam_bytes = align256((long long)sizeof(CamDev) * nk);
+    const long long need = cam_bytes + 4 * tab_floats;
     HIP_TRY(ctx, hipEventSynchronize(ctx->cams_evt));
-    if (nk > ctx->cams_cap) {
-        int cap = std::max(nk, 64);
+    if (need > ctx->cams_cap) {
+        const long long cap = std::max(need, (long long)sizeof(CamDev) * 64);
         HIP_TRY(ctx, hipEventSynchronize(ctx->cams_done));  // no kernel reads the old table any more
         (void)hipFree(ctx->cams_dev);
         (void)hipHostFree(ctx->cams_host);
         ctx->cams_dev = nullptr;
         ctx->cams_host = nullptr;
         ctx->cams_cap = 0;
-        HIP_TRY(ctx, hipMalloc((void **)&ctx->cams_dev, sizeof(CamDev) * cap));
-        HIP_TRY(ctx, hipHostMalloc((void **)&ctx->cams_host, sizeof(CamDev) * cap, hipHostMallocDefault));
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->cams_dev, cap));
+        HIP_TRY(ctx, hipHostMalloc((void **)&ctx->cams_host, cap, hipHostMallocDefault));
         ctx->cams_cap = cap;
+    }
+    CamDev *cd = (CamDev *)ctx->cams_host;
+    float *tabs = (float *)(ctx->cams_host + cam_bytes);
+    for (auto &e : tab_of) {
+        const int W = (int)(e.first >> 32), H = (int)(e.first & 0xffffffff);
+        scan_tables(W, H, tabs + e.second, tabs + e.second + W / 4, tabs + e.second + W / 2);
     }
     for (int k = 0; k < nk; k++) {
         const tgv_camera &c = cams_host[keep[k]];
-        CamDev &d = ctx->cams_host[k];
+        CamDev &d = cd[k];
+        memset(&d, 0, sizeof(d));
         memcpy(d.R, c.R, sizeof(d.R));
         memcpy(d.t, c.t, sizeof(d.t));
         d.fx = c.fx;
@@ -335,23 +378,54 @@ extern "C" tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32
         d.cx = c.cx;
         d.cy = c.cy;
         d.vote = c.vote;
-        d.pyr = keep[k];
-        d.pad[0] = d.pad[1] = 0;
+        d.model = c.model;
+        d.W = c.width;
+        d.H = c.height;
+        const PyrGeom g = pyr_geom(c.width, c.height);
+        d.L = g.L;
+        for (int l = 0; l < g.L; l++) d.lvl[l] = (int)g.off[l];
+        d.base = offs[keep[k]];
+        d.tab = cam_tab[k];
     }
-    PyrGeom g = pyr_geom(W, H);
-    if (g.L > 24) return fail(ctx, TGV_E_INVAL, "image too large");
     if (nk > 0) {
         // the previous call's kernel (perhaps on another stream) is done with the table
         HIP_TRY(ctx, hipStreamWaitEvent(S(stream), ctx->cams_done, 0));
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->cams_dev, ctx->cams_host, sizeof(CamDev) * nk, hipMemcpyHostToDevice,
-                                    S(stream)));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->cams_dev, ctx->cams_host, need, hipMemcpyHostToDevice, S(stream)));
         HIP_TRY(ctx, hipEventRecord(ctx->cams_evt, S(stream)));
     }
-    launch_histograms(pyr, g, ctx->cams_dev, nk, *grid, *bins, hist, S(stream));
+    launch_histograms(pyr, (const CamDev *)ctx->cams_dev, nk, (const float *)(ctx->cams_dev + cam_bytes), *grid,
+                      *bins, accumulate, hist, S(stream));
     tgv_status r = check_launch(ctx, "histograms");
     if (r != TGV_OK) return r;
     HIP_TRY(ctx, hipEventRecord(ctx->cams_done, S(stream)));
     return TGV_OK;
+}
+
+extern "C" tgv_status tgv_build_histograms(tgv_ctx *ctx, const float *pyr, int32_t W, int32_t H,
+                                           const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid,
+                                           const tgv_bins *bins, uint16_t *hist, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (W < 1 || H < 1 || n_cams < 0 || !cams_host) return fail(ctx, TGV_E_INVAL, "tgv_build_histograms: bad arguments");
+    for (int c = 0; c < n_cams; c++)
+        if (cams_host[c].width != W || cams_host[c].height != H)
+            return fail(ctx, TGV_E_INVAL, "camera %d is %dx%d, pyramids are %dx%d", c, cams_host[c].width,
+                        cams_host[c].height, W, H);
+    const long long stride = pyr_geom(W, H).cam_stride;
+    std::vector<int64_t> offs(n_cams > 0 ? n_cams : 1);
+    for (int c = 0; c < n_cams; c++) offs[c] = stride * c;
+    return histograms_impl(ctx, "tgv_build_histograms", pyr, offs.data(), cams_host, n_cams, grid, bins, false, 0,
+                           hist, stream);
+}
+
+extern "C" tgv_status tgv_build_histograms_ex(tgv_ctx *ctx, const float *pyr, const int64_t *pyr_offsets_host,
+                                              const tgv_camera *cams_host, int32_t n_cams, const tgv_grid *grid,
+                                              const tgv_bins *bins, int32_t flags, int32_t prior_votes,
+                                              uint16_t *hist, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if ((n_cams > 0 && !pyr_offsets_host) || (flags & ~TGV_HIST_ACCUMULATE))
+        return fail(ctx, TGV_E_INVAL, "tgv_build_histograms_ex: bad arguments");
+    return histograms_impl(ctx, "tgv_build_histograms_ex", pyr, pyr_offsets_host, cams_host, n_cams, grid, bins,
+                           (flags & TGV_HIST_ACCUMULATE) != 0, prior_votes, hist, stream);
 }
 
 // ===========================================================================
@@ -985,4 +1059,20 @@ extern "C" tgv_status tgv_solve_coarse_to_fine(tgv_ctx *ctx, const float *pyr, i
         (void)hipFree(u[k]);
     }
     return r;
+}
+
+
+// ===========================================================================
+// streaming copy (measurement)
+// ===========================================================================
+extern "C" tgv_status tgv_stream_copy(tgv_ctx *ctx, const void *src, void *dst, int64_t bytes, int32_t variant,
+                                      void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!src || !dst || bytes < 0 || (bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15) ||
+        !stream_copy_variant_ok(variant))
+        return fail(ctx, TGV_E_INVAL, "tgv_stream_copy: bad arguments");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (bytes == 0) return TGV_OK;
+    launch_stream_copy(src, dst, bytes / 16, variant, ctx->cus, S(stream));
+    return check_launch(ctx, "stream copy");
 }

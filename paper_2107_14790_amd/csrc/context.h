@@ -11,10 +11,11 @@ struct tgv_ctx {
     int device;
     int cus;  // compute units of the device
     std::string err;
-    // pinned staging for the camera table + its device copy
-    tgv::CamDev *cams_host;
-    tgv::CamDev *cams_dev;
-    int cams_cap;
+    // pinned staging for the camera table and the scans' boundary tables,
+    // and its device copy (bytes)
+    char *cams_host;
+    char *cams_dev;
+    long long cams_cap;
     hipEvent_t cams_evt;   // after the upload of the staging buffer
     hipEvent_t cams_done;  // after the last kernel that read cams_dev
     // energy reduction scratch

@@ -48,15 +48,22 @@ struct PyrGeom {
     int w[24], h[24];
 };
 
-// A camera as the histogram kernel reads it (uniform per loop trip).
+// A camera as the histogram kernel reads it (uniform per loop trip): its
+// pose and intrinsics, its own image size and pyramid, and for a 360-degree
+// scan the offset of its boundary tables.
 struct CamDev {
     float R[9];
     float t[3];
     float fx, fy, cx, cy;
     int vote;
-    int pyr;  // index of its pyramid in the packed buffer
-    int pad[2];
+    int model;       // TGV_MODEL_PINHOLE or TGV_MODEL_SCAN360
+    int W, H;        // level-0 size
+    int L;           // pyramid levels
+    int tab;         // scan: float offset of its C, S (W/4 each) and K (H) tables
+    long long base;  // float offset of its pyramid in the packed buffer
+    int lvl[24];     // float offset of level l from base
 };
+static_assert(sizeof(CamDev) == 192, "CamDev layout");
 
 // Energy reduction output (device): primal parts (3), dual, nonfinite.
 struct EnergyOut {
@@ -117,13 +124,19 @@ void launch_energy(int storage, const SolveBufs &b, const Dims &d, const Coef &c
                    double *partials, int nparts, EnergyOut *out, hipStream_t s);
 int energy_partials(const Dims &d);
 void launch_pyramids(const float *depth, int ncam, const PyrGeom &g, float *pyr, hipStream_t s);
-void launch_histograms(const float *pyr, const PyrGeom &g, const CamDev *cams, int ncam, const tgv_grid &grid,
-                       const tgv_bins &bins, uint16_t *hist, hipStream_t s);
+// votes of ncam cameras (tables: the scans' boundary tables); accumulate:
+// add to hist's counts instead of overwriting them
+void launch_histograms(const float *pyr, const CamDev *cams, int ncam, const float *tables, const tgv_grid &grid,
+                       const tgv_bins &bins, bool accumulate, uint16_t *hist, hipStream_t s);
+// the scans' boundary tables of a W x H equirectangular map (host)
+void scan_tables(int W, int H, float *C, float *S, float *K);
 void launch_fill(float *p, float v, long long n, hipStream_t s);
 void launch_fill_bytes0(void *p, long long nbytes, hipStream_t s);
 void launch_convert(const void *src, int src_storage, void *dst, int dst_storage, long long n, hipStream_t s);
 
 PyrGeom pyr_geom(int W, int H);
+bool stream_copy_variant_ok(int variant);
+void launch_stream_copy(const void *src, void *dst, long long n4, int variant, int cus, hipStream_t s);
 int extract_blocks(const Dims &d);
 int extract_runs(const Dims &d);
 void launch_prolongate(const float *uc, const Dims &dc, float *uf, const Dims &df, hipStream_t s);

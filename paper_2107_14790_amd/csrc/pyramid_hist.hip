@@ -74,12 +74,71 @@ void launch_pyramids(const float *depth, int ncam, const PyrGeom &g, float *pyr,
     }
 }
 
+// Boundary tables of an equirectangular W x H scan (host; W a multiple of
+// 4): C[i] = cos(2 pi i / W), S[i] = sin(2 pi i / W) for i < W/4 (one
+// quadrant's column boundaries), K[j] = cos(pi j / H) for j < H (row
+// boundaries), each evaluated in double and rounded to float.
+void scan_tables(int W, int H, float *C, float *S, float *K) {
+    for (int i = 0; i < W / 4; i++) {
+        const double a = (6.283185307179586 * (double)i) / (double)W;
+        C[i] = (float)cos(a);
+        S[i] = (float)sin(a);
+    }
+    for (int j = 0; j < H; j++) {
+        const double a = (3.141592653589793 * (double)j) / (double)H;
+        K[j] = (float)cos(a);
+    }
+}
+
+// Column of scanner-frame direction (x, y) in an equirectangular map of W
+// columns: turn it by a multiple of -90 degrees into the first quadrant
+// (exact), then count the quadrant's boundaries at or before it,
+//   #{i in [1, W/4) : C[i] y' - S[i] x' >= 0}  (each product rounded).
+// The count is monotone in i (C falls, S rises, x', y' >= 0), so it is
+// found by walking from an atan2 estimate to where the test changes: a few
+// table reads instead of W/4, and the same integer as counting them all.
+__device__ __forceinline__ int scan_column(float x, float y, int W, const float *__restrict__ C,
+                                           const float *__restrict__ S) {
+    int q;
+    float xp, yp;
+    if (x > 0.0f && y >= 0.0f) { q = 0; xp = x; yp = y; }
+    else if (x <= 0.0f && y > 0.0f) { q = 1; xp = y; yp = -x; }
+    else if (x < 0.0f && y <= 0.0f) { q = 2; xp = -x; yp = -y; }
+    else if (x >= 0.0f && y < 0.0f) { q = 3; xp = -y; yp = x; }
+    else { q = 0; xp = x; yp = y; }
+    const int Q = W >> 2;
+    int c;
+    if (xp == 0.0f && yp == 0.0f) {
+        c = Q - 1;  // on the scanner's axis every test reads 0 >= 0
+    } else {
+        const float est = atan2f(yp, xp) * ((float)W * 0.159154943f);
+        c = est > 0.0f ? (int)est : 0;
+        c = c < Q - 1 ? c : Q - 1;
+        auto at_or_before = [&](int i) { return C[i] * yp - S[i] * xp >= 0.0f; };
+        while (c + 1 < Q && at_or_before(c + 1)) c++;
+        while (c > 0 && !at_or_before(c)) c--;
+    }
+    return q * Q + c;
+}
+
+// Row of direction z (of length rho) in an equirectangular map of H rows:
+// #{j in [1, H) : z <= K[j] rho}, monotone in j, walked from an acos estimate.
+__device__ __forceinline__ int scan_row(float z, float rho, int H, const float *__restrict__ K) {
+    const float ct = fminf(1.0f, fmaxf(-1.0f, z * __builtin_amdgcn_rcpf(rho)));
+    const float est = acosf(ct) * ((float)H * 0.318309886f);
+    int r = est > 0.0f ? (int)est : 0;
+    r = r < H - 1 ? r : H - 1;
+    while (r + 1 < H && z <= K[r + 1] * rho) r++;
+    while (r > 0 && !(z <= K[r] * rho)) r--;
+    return r;
+}
+
 // One thread per voxel; the camera loop is uniform, so camera parameters
 // come through scalar loads.  Counts live in two 64-bit registers as four
 // 16-bit fields each (the host rules out carries between fields).
-__global__ void __launch_bounds__(256) k_hist(const float *__restrict__ pyr, PyrGeom g, const CamDev *__restrict__ cams,
-                                              int ncam, tgv_grid grid, int nbins, int rule, float delta, float eta,
-                                              uint16_t *__restrict__ hist) {
+__global__ void __launch_bounds__(256) k_hist(const float *__restrict__ pyr, const CamDev *__restrict__ cams, int ncam,
+                                              const float *__restrict__ tables, tgv_grid grid, int nbins, int rule,
+                                              float delta, float eta, int accumulate, uint16_t *__restrict__ hist) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y * blockDim.y + threadIdx.y;
     int k = blockIdx.z;
@@ -88,10 +147,15 @@ __global__ void __launch_bounds__(256) k_hist(const float *__restrict__ pyr, Pyr
     const float X = grid.origin[0] + ((float)i + 0.5f) * h;
     const float Y = grid.origin[1] + ((float)j + 0.5f) * h;
     const float Z = grid.origin[2] + ((float)k + 0.5f) * h;
-    const float Wf = (float)g.W, Hf = (float)g.H;
     const float half = (float)(nbins - 1) / 2.0f;
     const float nbf = (float)nbins;
+    const long long idx = (long long)i + (long long)grid.nx * (j + (long long)grid.ny * k);
     uint64_t lo = 0, hi = 0;
+    if (accumulate) {
+        const uint4 w = *reinterpret_cast<const uint4 *>(hist + 8 * idx);
+        lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
+        hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
+    }
     for (int c = 0; c < ncam; c++) {
         const CamDev &cm = cams[c];
         float xc[3];
@@ -102,25 +166,39 @@ __global__ void __launch_bounds__(256) k_hist(const float *__restrict__ pyr, Pyr
             acc = acc + cm.R[3 * r + 2] * Z;
             xc[r] = acc + cm.t[r];
         }
-        float z = xc[2];
-        if (!(z > 0.0f)) continue;
-        float px = cm.fx * (xc[0] / z) + cm.cx;
-        float py = cm.fy * (xc[1] / z) + cm.cy;
-        if (!(px >= 0.0f && px < Wf && py >= 0.0f && py < Hf)) continue;
-        float s = (h * cm.fx) / z;
+        float dist, px, py;
+        if (cm.model == TGV_MODEL_PINHOLE) {
+            const float z = xc[2];
+            if (!(z > 0.0f)) continue;
+            px = cm.fx * (xc[0] / z) + cm.cx;
+            py = cm.fy * (xc[1] / z) + cm.cy;
+            if (!(px >= 0.0f && px < (float)cm.W && py >= 0.0f && py < (float)cm.H)) continue;
+            dist = z;
+        } else {
+            float r2 = xc[0] * xc[0];
+            r2 = r2 + xc[1] * xc[1];
+            r2 = r2 + xc[2] * xc[2];
+            const float rho = sqrtf(r2);
+            if (!(rho > 0.0f)) continue;
+            const float *tb = tables + cm.tab;
+            px = (float)scan_column(xc[0], xc[1], cm.W, tb, tb + (cm.W >> 2));
+            py = (float)scan_row(xc[2], rho, cm.H, tb + (cm.W >> 1));
+            dist = rho;
+        }
+        float s = (h * cm.fx) / dist;
         int l = 0;
         if (s >= 1.0f) {
             l = ilogbf(s);
-            if (l > g.L - 1) l = g.L - 1;
+            if (l > cm.L - 1) l = cm.L - 1;
         }
-        int wl = g.w[l], hl = g.h[l];
+        const int wl = ((cm.W - 1) >> l) + 1, hl = ((cm.H - 1) >> l) + 1;
         int ix = (int)floorf(ldexpf(px, -l));
         int iy = (int)floorf(ldexpf(py, -l));
         ix = ix > wl - 1 ? wl - 1 : ix;
         iy = iy > hl - 1 ? hl - 1 : iy;
-        float dep = pyr[(long long)cm.pyr * g.cam_stride + g.off[l] + (long long)iy * wl + ix];
+        float dep = pyr[cm.base + cm.lvl[l] + (long long)iy * wl + ix];
         if (dep == 0.0f) continue;
-        float a = dep - z;
+        float a = dep - dist;
         if (a < -eta) continue;
         float an = fminf(1.0f, fmaxf(-1.0f, a / delta));
         int bin;
@@ -136,16 +214,15 @@ __global__ void __launch_bounds__(256) k_hist(const float *__restrict__ pyr, Pyr
     w.y = (uint32_t)(lo >> 32);
     w.z = (uint32_t)hi;
     w.w = (uint32_t)(hi >> 32);
-    long long idx = (long long)i + (long long)grid.nx * (j + (long long)grid.ny * k);
     *reinterpret_cast<uint4 *>(hist + 8 * idx) = w;
 }
 
-void launch_histograms(const float *pyr, const PyrGeom &g, const CamDev *cams, int ncam, const tgv_grid &grid,
-                       const tgv_bins &bins, uint16_t *hist, hipStream_t s) {
+void launch_histograms(const float *pyr, const CamDev *cams, int ncam, const float *tables, const tgv_grid &grid,
+                       const tgv_bins &bins, bool accumulate, uint16_t *hist, hipStream_t s) {
     float eta = bins.eta_over_delta * bins.delta;
     dim3 blk(64, 4, 1);
-    hipLaunchKernelGGL(k_hist, dim3((grid.nx + 63) / 64, (grid.ny + 3) / 4, grid.nz), blk, 0, s, pyr, g, cams, ncam,
-                       grid, bins.num_bins, bins.rule, bins.delta, eta, hist);
+    hipLaunchKernelGGL(k_hist, dim3((grid.nx + 63) / 64, (grid.ny + 3) / 4, grid.nz), blk, 0, s, pyr, cams, ncam,
+                       tables, grid, bins.num_bins, bins.rule, bins.delta, eta, accumulate ? 1 : 0, hist);
 }
 
 // ---------------------------------------------------------------------------

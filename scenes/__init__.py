@@ -656,69 +656,12 @@ def city_blocks(scene: Scene, n_blocks: int = 512, e_min: int = 32, e_max: int =
 
 
 # ----------------------------------------------------------------------------
-# 360-degree scans (terrestrial LIDAR, Sec. 3.1) as six cube-face depth maps
+# camera sets
 # ----------------------------------------------------------------------------
-_CUBE_FACES = [((1.0, 0.0, 0.0), (0.0, 0.0, 1.0)), ((-1.0, 0.0, 0.0), (0.0, 0.0, 1.0)),
-               ((0.0, 1.0, 0.0), (0.0, 0.0, 1.0)), ((0.0, -1.0, 0.0), (0.0, 0.0, 1.0)),
-               ((0.0, 0.0, 1.0), (0.0, 1.0, 0.0)), ((0.0, 0.0, -1.0), (0.0, 1.0, 0.0))]
-
-
-def scan_cameras(center, W: int = 256, vote: int = 5) -> Cameras:
-    """A 360-degree scanner at `center` as six 90-degree pinhole faces
-    (f = W/2, principal point at the centre) covering every direction once;
-    each face casts votes of weight `vote` (5 for near noise-free LIDAR)."""
-    c = np.asarray(center, dtype=np.float64)
-    Rs, ts = [], []
-    for fwd, up in _CUBE_FACES:
-        R, t = look_at(c, c + np.asarray(fwd), up)
-        Rs.append(R)
-        ts.append(t)
-    return make_cameras(Rs, ts, W / 2.0, W / 2.0, W / 2.0, W / 2.0, W, W, vote=vote)
-
-
 def concat_cameras(a: Cameras, b: Cameras) -> Cameras:
     return Cameras(np.concatenate([a.R, b.R]), np.concatenate([a.t, b.t]), np.concatenate([a.intr, b.intr]),
                    np.concatenate([a.wh, b.wh]), np.concatenate([a.vote, b.vote]),
                    np.concatenate([a.model, b.model]))
-
-
-def terrain_scans(seed: int = 2, positions=((0.25, 0.25), (0.75, 0.25), (0.25, 0.75), (0.75, 0.75)),
-                  height: float = 0.03, W: int = 1024, lattice: int = 2048, hurst: float = 0.8,
-                  amplitude: float = 0.2, sigma_vox: float = 0.05, n: int = 256, device: str = "cpu"):
-    """Terrestrial 360-degree scans of the terrain of terrain_scene (same
-    seed, same heightfield): one scanner `height` above the ground at each
-    (x, y) position, six W x W faces each (vote 5), depth along every pixel
-    ray that descends onto the terrain (0 elsewhere), N(0, (sigma_vox h)^2)
-    noise on z and no outliers.  Returns (depth [6 k, W, W] float32, cams)."""
-    z01 = fbm_heightfield(lattice, hurst, seed)
-    hf = HeightField(z01, base=0.5, amplitude=amplitude)
-    Rs, ts, depth = [], [], []
-    h = float(np.float32(1.0 / n))
-    for (x, y) in positions:
-        C = np.array([x, y, float(hf([x], [y])[0]) + height])
-        cams_k = scan_cameras(C, W)
-        for k in range(len(cams_k)):
-            depth.append(heightfield_depth(cams_k, k, hf, device=device))
-        Rs.extend(list(cams_k.R))
-        ts.extend(list(cams_k.t))
-    cams = make_cameras(Rs, ts, W / 2.0, W / 2.0, W / 2.0, W / 2.0, W, W, vote=5)
-    rng = np.random.default_rng(seed + 2000)
-    grid = Grid(np.zeros(3, dtype=np.float32), h, (n, n, n), 0)
-    return add_noise(np.stack(depth), cams, grid, sigma_vox * h, 0.0, rng), cams
-
-
-def scan_sphere_scene(center=(2.2, 0.4, 0.3), W: int = 128, n: int = 32, extent: float = 1.5, seed: int = 11,
-                      sigma: float = 0.001) -> Scene:
-    """The unit sphere seen by one 360-degree scanner (vote 5, low noise, no
-    outliers) plus, for mixing, the eight ring cameras of sphere_scene."""
-    scan = scan_cameras(center, W)
-    ring = sphere_scene(n=n, extent=extent, sigma=0.0, outlier_frac=0.0)
-    h = np.float32(2.0 * extent / n)
-    grid = Grid(np.full(3, -extent, dtype=np.float32), float(h), (n, n, n), 0)
-    clean = np.stack([sphere_depth(scan, k) for k in range(len(scan))])
-    rng = np.random.default_rng(seed)
-    d_scan = add_noise(clean, scan, grid, sigma, 0.0, rng)
-    return Scene(d_scan, scan, grid, name="scan-sphere")
 
 
 # ----------------------------------------------------------------------------

@@ -140,25 +140,24 @@ def test_bench_solve_bit_identical_to_per_voxel_kernels(terrain):
 
 
 def test_scan_histograms_on_random_voxels_bit_exact(terrain):
-    """Four terrestrial 360-degree scans (six 1024^2 faces each, vote 5)
-    added to the 64 stereo maps: histograms of the whole block on random
-    voxels against the oracle."""
+    """Four terrestrial 360-degree scans (equirectangular, 4096 x 2048,
+    vote 5) fused with the 64 stereo maps of 1024^2 in one call: histograms
+    of the whole block on random voxels against the oracle."""
     import paper_2107_14790_amd as tgv
     ctx, sc = terrain["ctx"], terrain["sc"]
-    say("terrain scans: 4 scanners x 6 faces 1024^2")
-    sd, scams = scenes.terrain_scans(n=N, device="cuda")
-    depth = np.concatenate([sc.depth, sd])
+    say("terrain scans: 4 scanners 4096 x 2048")
+    sd, scams = scenes.terrain_scans360(n=N, device="cuda")
     cams = scenes.concat_cameras(sc.cams, scams)
-    H, W = depth.shape[1:]
-    pyr = ctx.build_pyramids(torch.from_numpy(depth).cuda())
-    hist = ctx.build_histograms(pyr, W, H, tgv.cameras_from(cams), terrain["g"])
+    pyr, offs = ctx.build_pyramids_mixed([torch.from_numpy(sc.depth).cuda(), torch.from_numpy(sd).cuda()])
+    hist = ctx.build_histograms_ex(pyr, offs, cams, terrain["g"])
     got = hist.cpu().numpy().view(np.uint16)
     rng = np.random.default_rng(2563)
     vox = rng.choice(N ** 3, size=20000, replace=False)
     say("oracle on 20000 random voxels x", len(cams), "maps")
-    ref, _ = oracle.histograms(scenes.Scene(depth, cams, sc.grid), oracle.pyramids(depth), vox=vox)
+    opyr = np.concatenate([terrain["opyr"], oracle.pyramids(sd)])
+    ref, _ = oracle.histograms(scenes.Scene(None, cams, sc.grid), opyr, vox=vox)
     assert np.array_equal(got[vox], ref)
-    # the scans add votes of weight 5 near the ground under the scanners
+    # the scans add votes of weight 5 near the ground around the scanners
     assert (got[vox].astype(np.int64) - terrain["hist_np"][vox]).max() >= 5
 
 
@@ -210,3 +209,70 @@ def test_zero_level_of_the_solved_block(terrain):
     assert len(ref) > 0
     got = {r.tobytes() for r in pts.view(np.uint32)}
     assert all(r.tobytes() in got for r in ref.view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# The whole block against the oracle at the benchmark's iteration count.
+# Both sides advance together in chunks of CHUNK iterations (the GPU on a
+# resumable state with the library's default schedule, two iterations per
+# pass here, as the benchmark runs; the oracle on its own float64 state with
+# its per-voxel loops on the host's cores, bit-identical to its serial run);
+# each chunk is compared element by element over all 256^3 voxels.  A GPU
+# solve resumed in chunks is bit-identical to one uninterrupted solve, which
+# the last test checks against the benchmark's own call.
+# ---------------------------------------------------------------------------
+CHUNK = 200
+FULL_ITERS = 1000
+
+
+@pytest.fixture(scope="module")
+def whole_block(terrain):
+    import os
+    import paper_2107_14790_amd as tgv
+    sc = terrain["sc"]
+    k = max(1, min(16, os.cpu_count() or 1))
+    say(f"oracle histograms of all {N}^3 voxels x 64 maps on {k} threads")
+    with oracle.threads(k):
+        h_ref, _ = oracle.histograms(sc, terrain["opyr"])
+    assert np.array_equal(terrain["hist_np"], h_ref), "whole-block histograms differ from the oracle"
+    ctx, g = terrain["ctx"], terrain["g"]
+    st = tgv.State(ctx, g)
+    st.reset(torch.zeros(N ** 3, device="cuda"))
+    return dict(k=k, h_ref=h_ref, gpu=st, ora=None, done=[0])
+
+
+def advance_to(wb, terrain, iters):
+    import paper_2107_14790_amd as tgv
+    ctx, g = terrain["ctx"], terrain["g"]
+    while wb["done"][0] < iters:
+        step = min(CHUNK, iters - wb["done"][0])
+        ctx.solve(g, terrain["hist"], None, tgv.Params(iters=step), state=wb["gpu"])
+        with oracle.threads(wb["k"]):
+            wb["ora"] = oracle.solve(wb["h_ref"], (N, N, N), scenes.default_bins(), step, state=wb["ora"])
+        wb["done"][0] += step
+        say(f"both sides at {wb['done'][0]} iterations")
+
+
+@pytest.mark.parametrize("iters", list(range(CHUNK, FULL_ITERS + 1, CHUNK)))
+def test_whole_block_matches_oracle(whole_block, terrain, iters):
+    """max |u_gpu - u_oracle| <= 1e-4 over every voxel of the 256^3 block
+    after 200, 400, ..., 1000 iterations."""
+    advance_to(whole_block, terrain, iters)
+    got = whole_block["gpu"].export()["u"].cpu().numpy().astype(np.float64)
+    err = np.abs(got - whole_block["ora"].u)
+    say(f"{iters} iterations: max |u - u_oracle| = {err.max():.3g}, mean {err.mean():.3g}")
+    assert np.isfinite(got).all()
+    assert err.max() <= 1e-4
+
+
+def test_whole_block_benchmark_call_equals_chunked_solve(whole_block, terrain):
+    """The benchmark's call (a fresh 1000-iteration solve with the library's
+    defaults) gives the chunked solve's u bit for bit, so the oracle
+    comparison above holds for it."""
+    import paper_2107_14790_amd as tgv
+    advance_to(whole_block, terrain, FULL_ITERS)
+    ctx, g = terrain["ctx"], terrain["g"]
+    u = torch.zeros(N ** 3, device="cuda")
+    ctx.solve(g, terrain["hist"], u, tgv.Params(iters=FULL_ITERS))
+    chunked = whole_block["gpu"].export()["u"]
+    assert torch.equal(u, chunked)

@@ -533,23 +533,6 @@ def test_tvl1_matches_oracle(ctx):
     assert abs(stats["dual"] - D) <= 1e-4 * abs(D) + 1e-3
 
 
-# ---------------------------------------------------------------------------
-# 360-degree scans (six cube faces, vote 5) mixed with stereo depth maps
-# ---------------------------------------------------------------------------
-def test_scan_and_stereo_histograms_bit_exact(ctx):
-    say("360 scan + ring histograms")
-    scan = scenes.scan_sphere_scene()
-    ring = scenes.sphere_scene()
-    cams = scenes.Cameras(np.concatenate([ring.cams.R, scan.cams.R]), np.concatenate([ring.cams.t, scan.cams.t]),
-                          np.concatenate([ring.cams.intr, scan.cams.intr]), np.concatenate([ring.cams.wh, scan.cams.wh]),
-                          np.concatenate([ring.cams.vote, scan.cams.vote]))
-    sc = scenes.Scene(np.concatenate([ring.depth, scan.depth]), cams, ring.grid)
-    _, hist = gpu_hist(ctx, sc)
-    ref, mx = oracle.histograms(sc)
-    assert np.array_equal(hist, ref)
-    assert mx >= 5 and hist.max() >= 5
-
-
 def test_histogram_count_limit_exactly_65535(ctx):
     import paper_2107_14790_amd as tgv
     say("count limit 65535")

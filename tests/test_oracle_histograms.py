@@ -236,19 +236,6 @@ def test_scene_seeds_reproduce():
     assert (t1.depth > 0).mean() > 0.99
 
 
-def test_terrain_scan_generator_geometry():
-    """The scanner's downward face sees the ground `height` below it at the
-    image centre; the upward face sees nothing; every face votes 5."""
-    d, cams = scenes.terrain_scans(positions=((0.4, 0.6),), W=32, n=32, sigma_vox=0.0)
-    assert d.shape == (6, 32, 32) and len(cams) == 6 and set(cams.vote.tolist()) == {5}
-    up = [k for k in range(6) if cams.R[k][2, 2] > 0.99]      # camera z along world +Z
-    down = [k for k in range(6) if cams.R[k][2, 2] < -0.99]
-    assert len(up) == 1 and len(down) == 1
-    assert (d[up[0]] == 0).all()
-    assert (d[down[0]] > 0).all()
-    assert abs(float(d[down[0]][16, 16]) - 0.03) < 2e-3
-
-
 # ---------------------------------------------------------------------------
 # 360-degree scans (Sec. 3.1: terrestrial LIDAR as 360-degree depth maps,
 # vote 5 in Algorithm 1) as equirectangular range maps
