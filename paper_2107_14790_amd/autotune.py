@@ -1,28 +1,36 @@
-"""Tile-shape autotuner for the fused TGV kernel.
+"""Schedule and tile-shape autotuner for batched TGV solves.
 
-The fused kernel walks 64 x tile_y column tiles through chunks of tile_z
-planes.  The best shape depends on the block size (how many tiles fill the
-chip, how much of each chunk is halo) and on the storage precision.  The
-autotuner groups blocks into edge-size classes, times candidate shapes on
-the device through the batched C-ABI call (one representative batch per
-class, synthetic histograms, a few iterations) and keeps the fastest:
-tile_y for the whole batch (it is a kernel template parameter) and tile_z
-per class.  Results are cached in a JSON file keyed by device, storage and
-class.
+A batched solve runs either one fused iteration per persistent launch
+(schedule FUSED, tiles of 64 x tile_y columns with tile_y in {4, 8, 12}) or
+two (schedule FUSED2, temporal blocking, tile_y in {4, 6, 7}); each block's
+tiles walk chunks of tile_z planes.  tile_y is a kernel template parameter,
+so it is one per batch; tile_z is per block.  The best choice depends on
+the block sizes (how many tiles fill the chip, how much of each chunk is
+halo) and on the storage precision.
+
+The autotuner groups blocks into padded-edge classes, times every candidate
+(schedule, tile_y, tile_z) on a representative batch of each class through
+the batched C-ABI call (synthetic histograms, a few iterations), then picks
+the (schedule, tile_y) whose time summed over the classes (each scaled from
+its sample to the class's voxels) is least, and for each class the tile_z
+that is fastest at that pair.  Results are cached per device, storage and
+class.  The measurement is a function argument, so the search itself runs
+without a GPU (tests give it a model).
 """
 from __future__ import annotations
 
 import json
 import os
 import time
-from typing import Dict, List, Sequence
+from typing import Callable, Dict, List, Sequence
 
 import numpy as np
-import torch
 
-TILE_Y = (4, 8, 12)
+SCHED_NAMES = ("fused", "fused2")
+TILE_Y = {"fused": (4, 8, 12), "fused2": (4, 6, 7)}
 TILE_Z = (8, 16, 32, 64, 128)
 CLASS_EDGES = (48, 80, 128, 192, 1 << 30)  # padded edge upper bounds of the classes
+TUNE_ITERS = 9  # one dual step, four two-iteration launches (or eight one-iteration ones), one primal step
 
 
 def edge_class(n: Sequence[int]) -> int:
@@ -33,8 +41,51 @@ def edge_class(n: Sequence[int]) -> int:
     return len(CLASS_EDGES) - 1
 
 
+def candidates(shapes: Sequence[Sequence[int]]):
+    """(schedule, tile_y, tile_z) triples worth timing on blocks of these shapes:
+    chunks deeper than twice the deepest block are the same as the block."""
+    zmax = max(int(v[2]) for v in shapes)
+    out = []
+    for sched in SCHED_NAMES:
+        for ty in TILE_Y[sched]:
+            for tz in TILE_Z:
+                if tz <= 2 * zmax or tz == TILE_Z[0]:
+                    out.append((sched, ty, tz))
+    return out
+
+
+def pick(per_class: Dict[int, dict], weight: Dict[int, float], schedules=SCHED_NAMES) -> dict:
+    """Choose (schedule, tile_y) minimising the weighted sum over classes of
+    each class's best time at that pair, then each class's tile_z there.
+    per_class[c]["all"] maps "sched,ty,tz" to ms on the class's sample;
+    weight[c] scales the sample to the class's share of the batch; only the
+    given schedules are considered."""
+    pairs = {}
+    for cls, r in per_class.items():
+        for key, ms in r["all"].items():
+            sched, ty, _ = key.split(",")
+            if sched not in schedules:
+                continue
+            pairs.setdefault((sched, int(ty)), {}).setdefault(cls, []).append(ms)
+    total = {}
+    for pair, by_cls in pairs.items():
+        if set(by_cls) != set(per_class):
+            continue  # a pair not timed on every class
+        total[pair] = sum(weight[c] * min(v) for c, v in by_cls.items())
+    sched, ty = min(total, key=total.get)
+    tz_of = {}
+    for cls, r in per_class.items():
+        cands = {k: v for k, v in r["all"].items() if k.startswith(f"{sched},{ty},")}
+        tz_of[cls] = int(min(cands, key=cands.get).split(",")[2])
+    return {"schedule": sched, "tile_y": ty, "tile_z_of_class": tz_of, "predicted_ms": total[(sched, ty)]}
+
+
 class Autotuner:
-    def __init__(self, ctx, cache_path: str = None, iters: int = 8, reps: int = 3):
+    def __init__(self, ctx=None, cache_path: str = None, iters: int = TUNE_ITERS, reps: int = 3,
+                 measure: Callable = None, device_name: str = None):
+        """ctx: a libtgv Context (None when a `measure` model is given).
+        measure(shapes, storage, schedule, tile_y, tile_z) -> ms replaces the
+        GPU timing (for tests)."""
         self.ctx = ctx
         self.iters = iters
         self.reps = reps
@@ -43,54 +94,72 @@ class Autotuner:
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as f:
                 self.cache = json.load(f)
-        self.device_name = torch.cuda.get_device_name(ctx.device)
+        self.measure = measure or self._gpu_measure
+        if device_name is None:
+            import torch
+            device_name = torch.cuda.get_device_name(ctx.device)
+        self.device_name = device_name
+        self._batch = None
 
     def _key(self, storage: int, cls: int) -> str:
-        return f"{self.device_name}|s{storage}|c{cls}"
+        return f"{self.device_name}|s{storage}|c{cls}|v2"
 
-    def _time(self, states, hists, params) -> float:
+    # -- GPU measurement ---------------------------------------------------
+    def _gpu_measure(self, shapes, storage, sched, ty, tz) -> float:
+        import torch
+        import paper_2107_14790_amd as tgv
+        key = (tuple(tuple(s) for s in shapes), storage)
+        if self._batch is None or self._batch[0] != key:
+            self._release()
+            states, hists = [], []
+            for n in shapes:
+                g = tgv.grid_c((0, 0, 0), 1.0, n, min(2, (min(n) - 1) // 2))
+                st = tgv.State(self.ctx, g, storage)
+                nv = int(np.prod(n))
+                st.reset(torch.zeros(nv, device="cuda"))
+                h = torch.zeros((nv, 8), dtype=torch.int16, device="cuda")
+                h[:, 6] = 1
+                states.append(st)
+                hists.append(h)
+            self._batch = (key, states, hists)
+        _, states, hists = self._batch
+        p = tgv.Params(iters=self.iters, storage=storage, tile_y=ty, tile_z=tz,
+                       schedule=tgv.SCHED_FUSED2 if sched == "fused2" else tgv.SCHED_FUSED)
         s = torch.cuda.current_stream()
+        self.ctx.solve_batch(states, hists, p, tile_z=[tz] * len(states))  # warm
         best = float("inf")
         for _ in range(self.reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
-            self.ctx.solve_batch(states, hists, params, tile_z=[params.tile_z] * len(states))
+            self.ctx.solve_batch(states, hists, p, tile_z=[tz] * len(states))
             e1.record(s)
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1))
         return best
 
-    def tune_class(self, shapes: List[Sequence[int]], storage: int = 0, halo: int = 2, max_blocks: int = 16) -> dict:
+    def _release(self):
+        if self._batch is not None:
+            for st in self._batch[1]:
+                st.close()
+            self._batch = None
+
+    # -- search ------------------------------------------------------------
+    def tune_class(self, shapes: List[Sequence[int]], storage: int = 0, max_blocks: int = 16) -> dict:
         """Time every candidate on up to max_blocks representative shapes of one class."""
-        import paper_2107_14790_amd as tgv
         rng = np.random.default_rng(0)
-        pick = [shapes[i] for i in rng.choice(len(shapes), size=min(len(shapes), max_blocks), replace=False)]
-        states, hists = [], []
-        for n in pick:
-            g = tgv.grid_c((0, 0, 0), 1.0, n, min(halo, (min(n) - 1) // 2))
-            st = tgv.State(self.ctx, g, storage)
-            nv = int(np.prod(n))
-            st.reset(torch.zeros(nv, device="cuda"))
-            h = torch.zeros((nv, 8), dtype=torch.int16, device="cuda")
-            h[:, 6] = 1
-            states.append(st)
-            hists.append(h)
+        sample = [tuple(int(v) for v in shapes[i])
+                  for i in rng.choice(len(shapes), size=min(len(shapes), max_blocks), replace=False)]
         res = {}
-        for ty in TILE_Y:
-            for tz in TILE_Z:
-                if tz > 2 * max(int(v[2]) for v in pick):
-                    continue
-                p = tgv.Params(iters=self.iters, storage=storage, tile_y=ty, tile_z=tz)
-                self._time(states, hists, p)  # warm
-                res[f"{ty},{tz}"] = self._time(states, hists, p)
-        for st in states:
-            st.close()
+        for sched, ty, tz in candidates(sample):
+            res[f"{sched},{ty},{tz}"] = float(self.measure(sample, storage, sched, ty, tz))
+        self._release()
         best = min(res, key=res.get)
-        ty, tz = (int(v) for v in best.split(","))
-        return {"tile_y": ty, "tile_z": tz, "ms": res[best], "all": res}
+        return {"best": best, "ms": res[best], "all": res,
+                "sample_voxels": int(sum(int(np.prod(s)) for s in sample))}
 
     def tune(self, grids, storage: int = 0) -> dict:
-        """Per-class tile_z and one batch-wide tile_y for a list of block grids."""
+        """Schedule, batch-wide tile_y and per-block tile_z for a list of block
+        grids (objects with an `n` attribute)."""
         classes: Dict[int, list] = {}
         for g in grids:
             n = tuple(int(v) for v in g.n)
@@ -106,13 +175,23 @@ class Autotuner:
         if self.cache_path:
             with open(self.cache_path, "w") as f:
                 json.dump(self.cache, f, indent=1)
-        # tile_y: the class holding most voxels decides; tile_z: each class its best at that tile_y
-        weight = {cls: sum(int(np.prod(s)) for s in shapes) for cls, shapes in classes.items()}
-        main = max(weight, key=weight.get)
-        ty = per_class[main]["tile_y"]
-        tz_of = {}
-        for cls, r in per_class.items():
-            cands = {k: v for k, v in r["all"].items() if int(k.split(",")[0]) == ty}
-            tz_of[cls] = int(min(cands, key=cands.get).split(",")[1])
-        tile_z = [tz_of[edge_class(g.n)] for g in grids]
-        return {"tile_y": ty, "tile_z": tile_z, "classes": {str(k): v for k, v in per_class.items()}}
+        weight = {cls: sum(int(np.prod(s)) for s in shapes) / per_class[cls]["sample_voxels"]
+                  for cls, shapes in classes.items()}
+        choice = pick(per_class, weight)
+        tile_z = [choice["tile_z_of_class"][edge_class(g.n)] for g in grids]
+        by_schedule = {}
+        for sched in SCHED_NAMES:
+            c = pick(per_class, weight, (sched,))
+            by_schedule[sched] = {"tile_y": c["tile_y"], "predicted_ms": c["predicted_ms"],
+                                  "tile_z": [c["tile_z_of_class"][edge_class(g.n)] for g in grids]}
+        return {"schedule": choice["schedule"], "tile_y": choice["tile_y"], "tile_z": tile_z,
+                "predicted_ms": choice["predicted_ms"], "by_schedule": by_schedule,
+                "classes": {str(k): {"best": v["best"], "ms": v["ms"], "tile_z": choice["tile_z_of_class"][k]}
+                            for k, v in per_class.items()}}
+
+    @staticmethod
+    def params(tuned: dict, iters: int, storage: int = 0, flags: int = 0):
+        """Batched-solve parameters for a tune() result."""
+        import paper_2107_14790_amd as tgv
+        return tgv.Params(iters=iters, storage=storage, tile_y=tuned["tile_y"], flags=flags,
+                          schedule=tgv.SCHED_FUSED2 if tuned["schedule"] == "fused2" else tgv.SCHED_FUSED)

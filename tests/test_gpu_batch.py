@@ -199,3 +199,41 @@ def test_two_iteration_batch_equals_solo(ctx, storage, iters):
         f = fields(st)
         for k in f:
             assert np.array_equal(f[k], solo[i][k]), (i, k)
+
+
+def test_autotuned_batch_equals_solo(ctx):
+    """The autotuner's pick (schedule, tile_y, per-block tile_z, timed on this
+    GPU) runs the batch; every block's state equals its solo solve with the
+    library's defaults, bit for bit."""
+    import paper_2107_14790_amd as tgv
+    from paper_2107_14790_amd.autotune import Autotuner
+    say("autotuned batch")
+    blocks = make_blocks(7)
+    grids = [tgv.grid_c((0, 0, 0), 1.0, shape, halo) for shape, halo, _, _ in blocks]
+
+    class Gn:
+        def __init__(self, n):
+            self.n = n
+
+    tuned = Autotuner(ctx, iters=5, reps=1).tune([Gn(shape) for shape, _, _, _ in blocks])
+    say("tuned", tuned["schedule"], tuned["tile_y"], tuned["tile_z"])
+    assert len(tuned["tile_z"]) == len(blocks)
+    iters = 12
+    solo, states, hists = [], [], []
+    for (shape, halo, hist, u0), g in zip(blocks, grids):
+        h = torch.from_numpy(hist.view(np.int16)).cuda()
+        u = torch.from_numpy(u0).cuda()
+        a = tgv.State(ctx, g)
+        a.reset(u)
+        ctx.solve(g, h, None, tgv.Params(iters=iters), state=a)
+        solo.append(fields(a))
+        b = tgv.State(ctx, g)
+        b.reset(u)
+        states.append(b)
+        hists.append(h)
+    p = Autotuner.params(tuned, iters, flags=tgv.FLAG_GRAPH)
+    ctx.solve_batch(states, hists, p, tile_z=tuned["tile_z"])
+    for i, st in enumerate(states):
+        f = fields(st)
+        for k in f:
+            assert np.array_equal(f[k], solo[i][k]), (i, k)
