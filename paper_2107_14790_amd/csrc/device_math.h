@@ -44,20 +44,21 @@ struct Store<1> {
     static __device__ __forceinline__ void st(T *p, float v) { *p = to_half(v); }
 };
 
+// float32 -> bfloat16 bits, rounded to nearest even by gfx950's conversion
+// instruction (v_cvt_pk_bf16_f32); NaN stays NaN.  The same barrier as for
+// half keeps every kernel rounding the float32 value once.
+__device__ __forceinline__ uint16_t to_bf16_bits(float v) {
+    asm("" : "+v"(v));
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
 template <>
 struct Store<2> {
     using T = bf16_t;
     static __device__ __forceinline__ float ld(const T *p) {
         return __uint_as_float(((uint32_t)p->bits) << 16);
     }
-    // round to nearest even; NaN stays NaN
-    static __device__ __forceinline__ void st(T *p, float v) {
-        uint32_t u = __float_as_uint(v);
-        uint32_t r;
-        if ((u & 0x7fffffffu) > 0x7f800000u) r = (u >> 16) | 0x40u;
-        else r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-        p->bits = (uint16_t)r;
-    }
+    static __device__ __forceinline__ void st(T *p, float v) { p->bits = to_bf16_bits(v); }
 };
 
 // ---------------------------------------------------------------------------
