@@ -324,7 +324,12 @@ tgv_status tgv_prolongate(tgv_ctx *ctx, const tgv_grid *coarse, const float *u_c
  * histograms from the pyramids, starts from the prolongated coarser
  * solution (0 on the coarsest), keeps u frozen on its halo (the finest
  * level uses grid->halo, coarser levels none) and runs params->iters
- * iterations.  The finest u is written to u_out.  Synchronises. */
+ * iterations.  The finest u is written to u_out.  Asynchronous on
+ * `stream`: the levels' histograms, fields and solver state live in a
+ * context-owned workspace that is allocated on the first call and grown
+ * (after the previous call's work on it has finished) only when a call
+ * needs more; calls on other streams wait on the device for the previous
+ * call's use of it. */
 tgv_status tgv_solve_coarse_to_fine(tgv_ctx *ctx, const float *pyr, int32_t W, int32_t H, const tgv_camera *cams_host,
                                     int32_t n_cams, const tgv_grid *grid, const tgv_bins *bins,
                                     const tgv_params *params, int32_t levels, float *u_out, void *stream);

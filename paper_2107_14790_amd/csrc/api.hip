@@ -157,10 +157,13 @@ extern "C" tgv_status tgv_create(int device, tgv_ctx **out) {
     c->ext_scratch = nullptr;
     c->ext_cap = 0;
     c->ext_total_host = nullptr;
+    c->c2f_mem = nullptr;
+    c->c2f_cap = 0;
     if (hipHostMalloc((void **)&c->ext_total_host, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->cams_evt, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->cams_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->own_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->c2f_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->bt_evt, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->bt_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming) != hipSuccess ||
@@ -189,6 +192,7 @@ extern "C" void tgv_destroy(tgv_ctx *c) {
     (void)hipEventDestroy(c->cams_evt);
     (void)hipEventDestroy(c->cams_done);
     (void)hipEventDestroy(c->own_done);
+    (void)hipEventDestroy(c->c2f_done);
     (void)hipEventDestroy(c->bt_evt);
     (void)hipEventDestroy(c->bt_done);
     (void)hipEventDestroy(c->ev_a);
@@ -201,6 +205,7 @@ extern "C" void tgv_destroy(tgv_ctx *c) {
     (void)hipHostFree(c->bt_blocks_host);
     (void)hipHostFree(c->bt_tiles_host);
     (void)hipFree(c->ext_scratch);
+    (void)hipFree(c->c2f_mem);
     (void)hipHostFree(c->ext_total_host);
     delete c;
 }
@@ -622,38 +627,10 @@ extern "C" tgv_status tgv_energy(tgv_ctx *ctx, const tgv_state *st, const uint16
     return run_energy(ctx, st, hist, bins, params, stats_host, S(stream));
 }
 
-extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
-                                const tgv_params *params, float *u_io, tgv_state *state, tgv_stats *stats_host,
-                                void *stream) {
-    if (!ctx) return TGV_E_INVAL;
-    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad grid");
-    if (!bins_ok(bins)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad bins");
-    if (!params_ok(params)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad params");
-    if (!hist) return fail(ctx, TGV_E_INVAL, "tgv_solve: null hist");
-    if (!state && !u_io) return fail(ctx, TGV_E_INVAL, "tgv_solve: fresh solve needs u_io");
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = S(stream);
-    tgv_state *st = state;
-    if (st) {
-        if (!same_grid(st->grid, *grid) || st->storage != params->storage)
-            return fail(ctx, TGV_E_INVAL, "tgv_solve: state does not match grid/storage");
-    } else {
-        if (ctx->own && (!same_grid(ctx->own->grid, *grid) || ctx->own->storage != params->storage)) {
-            HIP_TRY(ctx, hipEventSynchronize(ctx->own_done));  // the last solve on it has finished
-            tgv_state_destroy(ctx->own);
-            ctx->own = nullptr;
-        }
-        if (!ctx->own) {
-            tgv_status r = tgv_state_create(ctx, grid, params->storage, &ctx->own);
-            if (r != TGV_OK) return r;
-        }
-        st = ctx->own;
-        st->grid = *grid;
-        HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->own_done, 0));  // a solve on another stream may still use it
-        tgv_status r = tgv_state_reset(ctx, st, u_io, stream);
-        if (r != TGV_OK) return r;
-    }
-    Dims d = make_dims(*grid);
+// params->iters iterations on a state (kernels only: nothing is allocated)
+static tgv_status advance(tgv_ctx *ctx, tgv_state *st, const uint16_t *hist, const tgv_bins *bins,
+                          const tgv_params *params, hipStream_t s) {
+    Dims d = make_dims(st->grid);
     Coef cf = make_coef(*params, *bins);
     int N = params->iters;
     if (N > 0) {
@@ -712,7 +689,44 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
         }
         st->fresh = false;
         st->iters_done += N;
-        tgv_status r = check_launch(ctx, "solve");
+        return check_launch(ctx, "solve");
+    }
+    return TGV_OK;
+}
+
+extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
+                                const tgv_params *params, float *u_io, tgv_state *state, tgv_stats *stats_host,
+                                void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad grid");
+    if (!bins_ok(bins)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad bins");
+    if (!params_ok(params)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad params");
+    if (!hist) return fail(ctx, TGV_E_INVAL, "tgv_solve: null hist");
+    if (!state && !u_io) return fail(ctx, TGV_E_INVAL, "tgv_solve: fresh solve needs u_io");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = S(stream);
+    tgv_state *st = state;
+    if (st) {
+        if (!same_grid(st->grid, *grid) || st->storage != params->storage)
+            return fail(ctx, TGV_E_INVAL, "tgv_solve: state does not match grid/storage");
+    } else {
+        if (ctx->own && (!same_grid(ctx->own->grid, *grid) || ctx->own->storage != params->storage)) {
+            HIP_TRY(ctx, hipEventSynchronize(ctx->own_done));  // the last solve on it has finished
+            tgv_state_destroy(ctx->own);
+            ctx->own = nullptr;
+        }
+        if (!ctx->own) {
+            tgv_status r = tgv_state_create(ctx, grid, params->storage, &ctx->own);
+            if (r != TGV_OK) return r;
+        }
+        st = ctx->own;
+        st->grid = *grid;
+        HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->own_done, 0));  // a solve on another stream may still use it
+        tgv_status r = tgv_state_reset(ctx, st, u_io, stream);
+        if (r != TGV_OK) return r;
+    }
+    {
+        tgv_status r = advance(ctx, st, hist, bins, params, s);
         if (r != TGV_OK) return r;
     }
     if (u_io) HIP_TRY(ctx, hipMemcpyAsync(u_io, st->u[st->xc], 4 * st->n, hipMemcpyDeviceToDevice, s));
@@ -721,6 +735,30 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
     return TGV_OK;
 }
 
+
+// A fresh solve (u = u_io, v = p = q = 0, params->iters iterations, u back
+// to u_io) on a state laid over `mem` (tgv_state_bytes(grid, storage) bytes,
+// 256-byte aligned): kernels and device copies only, nothing allocated.
+static tgv_status fresh_solve_on(tgv_ctx *ctx, void *mem, const tgv_grid *grid, const uint16_t *hist,
+                                 const tgv_bins *bins, const tgv_params *params, float *u_io, hipStream_t s) {
+    tgv_state st{};
+    st.grid = *grid;
+    st.storage = params->storage;
+    st.n = (long long)grid->nx * grid->ny * grid->nz;
+    st.owned = false;
+    st.mem = mem;
+    state_layout(&st);
+    // fresh start: u = u_io, v = p = q = 0 (fill kernels, no memset)
+    HIP_TRY(ctx, hipMemcpyAsync(st.u[0], u_io, 4 * st.n, hipMemcpyDeviceToDevice, s));
+    const long long sb = storage_bytes(st.storage);
+    launch_fill_bytes0(st.v[0], 3 * st.n * sb, s);
+    launch_fill_bytes0(st.p[0], 3 * st.n * sb, s);
+    launch_fill_bytes0(st.q[0], 6 * st.n * sb, s);
+    tgv_status r = advance(ctx, &st, hist, bins, params, s);
+    if (r != TGV_OK) return r;
+    HIP_TRY(ctx, hipMemcpyAsync(u_io, st.u[st.xc], 4 * st.n, hipMemcpyDeviceToDevice, s));
+    return check_launch(ctx, "fresh solve");
+}
 
 // ===========================================================================
 // batched solve
@@ -1031,33 +1069,51 @@ extern "C" tgv_status tgv_solve_coarse_to_fine(tgv_ctx *ctx, const float *pyr, i
         g[k].nz = (g[k - 1].nz + 1) / 2;
         g[k].halo = 0;
     }
-    std::vector<uint16_t *> hist(levels, nullptr);
-    std::vector<float *> u(levels, nullptr);
-    tgv_status r = TGV_OK;
-    for (int k = 0; k < levels && r == TGV_OK; k++) {
-        long long n = (long long)g[k].nx * g[k].ny * g[k].nz;
-        if (hipMalloc((void **)&hist[k], 16 * n) != hipSuccess || hipMalloc((void **)&u[k], 4 * n) != hipSuccess)
-            r = fail(ctx, TGV_E_NOMEM, "tgv_solve_coarse_to_fine: allocation failed");
+    // workspace: every level's histograms and u, then one solver state of
+    // the finest (largest) level that each level's solve lays itself over
+    std::vector<long long> off_h(levels), off_u(levels);
+    long long need = 0;
+    for (int k = 0; k < levels; k++) {
+        const long long n = (long long)g[k].nx * g[k].ny * g[k].nz;
+        off_h[k] = need;
+        need += align256(16 * n);
+        off_u[k] = need;
+        need += align256(4 * n);
     }
+    const long long off_state = need;
+    need += tgv_state_bytes(&g[0], params->storage);
+    if (need > ctx->c2f_cap) {
+        HIP_TRY(ctx, hipEventSynchronize(ctx->c2f_done));  // the last call's work on it has finished
+        (void)hipFree(ctx->c2f_mem);
+        ctx->c2f_mem = nullptr;
+        ctx->c2f_cap = 0;
+        if (hipMalloc(&ctx->c2f_mem, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, TGV_E_NOMEM, "tgv_solve_coarse_to_fine: cannot allocate %lld bytes", need);
+        }
+        ctx->c2f_cap = need;
+    }
+    HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->c2f_done, 0));  // a call on another stream may still use it
+    char *ws = (char *)ctx->c2f_mem;
+    tgv_status r = TGV_OK;
     for (int k = levels - 1; k >= 0 && r == TGV_OK; k--) {
         tgv_bins bk = *bins;
         bk.delta = bins->delta * (float)(1 << k);
-        r = tgv_build_histograms(ctx, pyr, W, H, cams_host, n_cams, &g[k], &bk, hist[k], stream);
+        uint16_t *hk = (uint16_t *)(ws + off_h[k]);
+        float *uk = (float *)(ws + off_u[k]);
+        r = tgv_build_histograms(ctx, pyr, W, H, cams_host, n_cams, &g[k], &bk, hk, stream);
         if (r != TGV_OK) break;
-        long long n = (long long)g[k].nx * g[k].ny * g[k].nz;
-        if (k == levels - 1) launch_fill(u[k], 0.0f, n, s);
-        else launch_prolongate(u[k + 1], make_dims(g[k + 1]), u[k], make_dims(g[k]), s);
-        r = tgv_solve(ctx, &g[k], hist[k], &bk, params, u[k], nullptr, nullptr, stream);
+        const long long n = (long long)g[k].nx * g[k].ny * g[k].nz;
+        if (k == levels - 1) launch_fill(uk, 0.0f, n, s);
+        else launch_prolongate((const float *)(ws + off_u[k + 1]), make_dims(g[k + 1]), uk, make_dims(g[k]), s);
+        r = fresh_solve_on(ctx, ws + off_state, &g[k], hk, &bk, params, uk, s);
     }
     if (r == TGV_OK) {
-        hipError_t e = hipMemcpyAsync(u_out, u[0], 4LL * g[0].nx * g[0].ny * g[0].nz, hipMemcpyDeviceToDevice, s);
+        hipError_t e = hipMemcpyAsync(u_out, ws + off_u[0], 4LL * g[0].nx * g[0].ny * g[0].nz,
+                                      hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) r = fail(ctx, TGV_E_DEVICE, "copy: %s", hipGetErrorString(e));
     }
-    (void)hipStreamSynchronize(s);
-    for (int k = 0; k < levels; k++) {
-        (void)hipFree(hist[k]);
-        (void)hipFree(u[k]);
-    }
+    HIP_TRY(ctx, hipEventRecord(ctx->c2f_done, s));
     return r;
 }
 

@@ -41,6 +41,10 @@ struct tgv_ctx {
     void *ext_scratch;
     long long ext_cap;
     unsigned long long *ext_total_host;
+    // coarse-to-fine workspace: every level's histograms and u, one state
+    void *c2f_mem;
+    long long c2f_cap;
+    hipEvent_t c2f_done;  // after the last call that used it
 };
 
 struct tgv_state {
