@@ -293,6 +293,28 @@ tgv_status tgv_state_import(tgv_ctx *ctx, tgv_state *st, const float *u, const f
 tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
                      const tgv_params *params, float *u_io, tgv_state *state, tgv_stats *stats_host, void *stream);
 
+/* Bytes of the fixed device workspace of tgv_solve_noalloc (64 MiB): a
+ * state of tgv_state_bytes(grid, storage) up to this size, e.g. blocks of
+ * up to 645 277 voxels (86^3) with float32 storage, 1 198 372 (106^3) with
+ * 16-bit storage. */
+#define TGV_NOALLOC_MAX_BYTES (64LL << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): a fresh
+ * solve as tgv_solve(ctx, grid, hist, bins, params, u_io, NULL, NULL,
+ * stream) gives, bit for bit, whose solver state lives in a fixed device
+ * array of TGV_NOALLOC_MAX_BYTES instead of a context-owned allocation.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine) and returns no statistics.  u_io: in = initial values and the
+ * frozen border, out = u.  TGV_E_INVAL if the block's state needs more than
+ * TGV_NOALLOC_MAX_BYTES (tgv_state_bytes(grid, params->storage)) or on the
+ * argument errors of tgv_solve.  Each GPU holds one such array for the
+ * life of the process, shared by every context and call on that GPU: calls
+ * that overlap on one GPU (other streams, other contexts or threads) race
+ * on it and give undefined results; calls in one stream are ordered. */
+tgv_status tgv_solve_noalloc(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
+                             const tgv_params *params, float *u_io, void *stream);
+
 /* Batched solve (many uneven blocks, Sec. 4.5: treetop leaves are
  * independent units, and small ones are processed together): advance each
  * of the n states by params->iters iterations.  Every iteration (or

@@ -25,6 +25,7 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF, SCHED_FUSED2, SCHED_AUTO = 0, 1, 2, 3, 4
 FLAG_GRAPH = 1
 FLAG_TVL1 = 2
+NOALLOC_MAX_BYTES = 64 << 20  # TGV_NOALLOC_MAX_BYTES
 MODEL_PINHOLE, MODEL_SCAN360 = 0, 1
 HIST_ACCUMULATE = 1
 STORAGE_NAMES = {"f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
@@ -96,6 +97,8 @@ _SIGS = {
     "tgv_state_import": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "tgv_solve": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT),
                                  _vp, _vp, ctypes.POINTER(StatsT), _vp]),
+    "tgv_solve_noalloc": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, ctypes.POINTER(BinsT),
+                                         ctypes.POINTER(ParamsT), _vp, _vp]),
     "tgv_energy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(BinsT), ctypes.POINTER(ParamsT),
                                   ctypes.POINTER(StatsT), _vp]),
     "tgv_extract_crossings": (ctypes.c_int, [_vp, ctypes.POINTER(GridT), _vp, _vp, ctypes.c_int64,
@@ -386,6 +389,17 @@ class Context:
                                        _ptr(u_io), state.h if state is not None else None,
                                        ctypes.byref(s) if stats else None, _stream(stream)))
         return stats_dict(s) if stats else None
+
+    def solve_noalloc(self, grid, hist: torch.Tensor, u_io: torch.Tensor, params: Params = None, bins: Bins = None,
+                      stream=None):
+        """Fresh solve whose state lives in the library's fixed device
+        workspace (no device allocation; blocks whose state fits in
+        NOALLOC_MAX_BYTES).  u_io: initial values in, u out."""
+        g = grid_from(grid)
+        p = (params or Params()).to_c()
+        b = (bins or Bins()).to_c(g.h)
+        self._check(self.lib.tgv_solve_noalloc(self.h, ctypes.byref(g), _ptr(hist), ctypes.byref(b), ctypes.byref(p),
+                                               _ptr(u_io), _stream(stream)))
 
     def solve_batch(self, states, hists, params: Params = None, bins: Bins = None, tile_z=None, stats: bool = False,
                     stream=None):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "context.h"
@@ -125,6 +126,32 @@ hipStream_t S(void *s) { return (hipStream_t)s; }
 
 }  // namespace
 
+// the fixed workspace of tgv_solve_noalloc and its per-device addresses
+constexpr int TGV_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[TGV_NOALLOC_MAX_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[TGV_MAX_DEVICES];
+
+// the device address of `scratch` on the current device `device`
+static tgv_status scratch_lookup(int device) {
+    if (device < 0 || device >= TGV_MAX_DEVICES) return TGV_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return TGV_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return TGV_E_DEVICE;
+    }
+    g_scratch_ptr[device] = ptr;
+    return TGV_OK;
+}
+
+static void *scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (device >= 0 && device < TGV_MAX_DEVICES) ? g_scratch_ptr[device] : nullptr;
+}
+
 // ===========================================================================
 // context
 // ===========================================================================
@@ -173,6 +200,10 @@ extern "C" tgv_status tgv_create(int device, tgv_ctx **out) {
         hipMalloc((void **)&c->eout_dev, sizeof(EnergyOut)) != hipSuccess ||
         hipHostMalloc((void **)&c->eout_host, sizeof(EnergyOut), hipHostMallocDefault) != hipSuccess) {
         delete c;
+        return TGV_E_DEVICE;
+    }
+    if (scratch_lookup(device) != TGV_OK) {
+        tgv_destroy(c);
         return TGV_E_DEVICE;
     }
     *out = c;
@@ -758,6 +789,33 @@ static tgv_status fresh_solve_on(tgv_ctx *ctx, void *mem, const tgv_grid *grid, 
     if (r != TGV_OK) return r;
     HIP_TRY(ctx, hipMemcpyAsync(u_io, st.u[st.xc], 4 * st.n, hipMemcpyDeviceToDevice, s));
     return check_launch(ctx, "fresh solve");
+}
+
+// ---------------------------------------------------------------------------
+// Fresh solve without allocation: the solver state lives in `scratch`, a
+// fixed array in device memory (one per GPU the library runs on, held until
+// the process ends).  Host code never passes the array's name to a kernel or
+// a copy: it is a host-side stand-in, not a device address.  tgv_create looks
+// up each device's address of the array once, with that device current, and
+// every use goes through that pointer.
+// ---------------------------------------------------------------------------
+extern "C" tgv_status tgv_solve_noalloc(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist,
+                                        const tgv_bins *bins, const tgv_params *params, float *u_io, void *stream) {
+    if (!ctx) return TGV_E_INVAL;
+    if (!grid_ok(grid)) return fail(ctx, TGV_E_INVAL, "tgv_solve_noalloc: bad grid");
+    if (!bins_ok(bins)) return fail(ctx, TGV_E_INVAL, "tgv_solve_noalloc: bad bins");
+    if (!params_ok(params)) return fail(ctx, TGV_E_INVAL, "tgv_solve_noalloc: bad params");
+    if (!hist || !u_io) return fail(ctx, TGV_E_INVAL, "tgv_solve_noalloc: null hist or u_io");
+    const long long need = tgv_state_bytes(grid, params->storage);
+    if (need < 0 || need > TGV_NOALLOC_MAX_BYTES)
+        return fail(ctx, TGV_E_INVAL,
+                    "tgv_solve_noalloc: the state of a %d x %d x %d block needs %lld bytes, more than the %lld "
+                    "of the fixed workspace",
+                    grid->nx, grid->ny, grid->nz, need, (long long)TGV_NOALLOC_MAX_BYTES);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    void *mem = scratch_of(ctx->device);
+    if (!mem) return fail(ctx, TGV_E_DEVICE, "tgv_solve_noalloc: no workspace address for device %d", ctx->device);
+    return fresh_solve_on(ctx, mem, grid, hist, bins, params, u_io, S(stream));
 }
 
 // ===========================================================================
