@@ -434,8 +434,11 @@ static void launch_batch_t(const BatchBlock *blocks, const int4 *tiles, int ntil
     if (ty == 4)
         hipLaunchKernelGGL((k_fused_batch<STORE, 4>), dim3(grid), dim3(TX * 7), 0, s, blocks, tiles, ntiles, counters,
                            cf, flip);
-    else if (ty == 7)  // the odd pass of a two-iteration batch, on its 64 x 7 tile table
+    else if (ty == 7)  // single passes of a two-iteration batch, on its 64 x 7 tile table
         hipLaunchKernelGGL((k_fused_batch<STORE, 7>), dim3(grid), dim3(TX * 10), 0, s, blocks, tiles, ntiles,
+                           counters, cf, flip);
+    else if (ty == 6)  // the same on a 64 x 6 table
+        hipLaunchKernelGGL((k_fused_batch<STORE, 6>), dim3(grid), dim3(TX * 9), 0, s, blocks, tiles, ntiles,
                            counters, cf, flip);
     else if (ty == 12)
         hipLaunchKernelGGL((k_fused_batch<STORE, 12>), dim3(grid), dim3(TX * 15), 0, s, blocks, tiles, ntiles,
@@ -456,8 +459,11 @@ static int batch_per_cu_t() {
 
 template <int STORE>
 static int batch_per_cu_s(int ty) {
-    return ty == 4 ? batch_per_cu_t<STORE, 4>()
-                   : (ty == 12 ? batch_per_cu_t<STORE, 12>() : (ty == 7 ? batch_per_cu_t<STORE, 7>() : batch_per_cu_t<STORE, 8>()));
+    return ty == 4    ? batch_per_cu_t<STORE, 4>()
+           : ty == 12 ? batch_per_cu_t<STORE, 12>()
+           : ty == 7  ? batch_per_cu_t<STORE, 7>()
+           : ty == 6  ? batch_per_cu_t<STORE, 6>()
+                      : batch_per_cu_t<STORE, 8>();
 }
 
 int batch_blocks_per_cu(int storage, int ty) {
