@@ -156,8 +156,18 @@ typedef struct {
  * (alpha1 |grad u| + lambda data, i.e. v held at 0 and q unused) instead of
  * the TGV model of Eq. 2: a solve of at least one iteration first sets the
  * state's v and q (both iterates) to 0, whatever they held, and they stay
- * 0. */
-enum { TGV_FLAG_GRAPH = 1, TGV_FLAG_TVL1 = 2 };
+ * 0.  TGV_FLAG_LEAVE_OPEN (tgv_solve on a caller state without u_io or
+ * statistics, tgv_solve_batch without statistics) leaves the state open:
+ * iteration n = iters_done has its dual half done and its primal half
+ * pending.  The next solve of an open state starts with a pass that
+ * completes that primal half fused with the next iteration's dual half, so
+ * a long solve cut into calls costs no extra passes; a solve without the
+ * flag closes the state (iters 0 closes it without advancing it).  The
+ * results are bit-identical to one uninterrupted solve.  An open state
+ * cannot be exported or evaluated (tgv_state_export, tgv_energy:
+ * TGV_E_INVAL) and continues with the model (TGV or TV-L1) it was opened
+ * with; tgv_state_reset and tgv_state_import close it. */
+enum { TGV_FLAG_GRAPH = 1, TGV_FLAG_TVL1 = 2, TGV_FLAG_LEAVE_OPEN = 4 };
 
 /* Energy statistics of a state, reduced in float64:
  *   primal = discrete Eq. 2 at (u, v);
@@ -326,7 +336,10 @@ tgv_status tgv_solve_noalloc(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t 
  * default); params->tile_y applies to all blocks.  With TGV_FLAG_GRAPH the
  * iteration loop is captured once in a HIP graph and replayed.  Results are
  * bit-identical to tgv_solve on each state alone.  stats_host: NULL or n
- * entries (synchronises).  All states must use params->storage. */
+ * entries (synchronises).  All states must use params->storage.  Open and
+ * closed states may be mixed: every state advances params->iters
+ * iterations (the open ones take one more batched pass than the closed
+ * ones, which start with their dual half). */
 tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const *states, const uint16_t *const *hist,
                            const tgv_bins *bins, const tgv_params *params, const int32_t *tile_z_host,
                            tgv_stats *stats_host, void *stream);

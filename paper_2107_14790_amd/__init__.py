@@ -25,6 +25,7 @@ STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
 SCHED_FUSED, SCHED_SPLIT, SCHED_FUSED_REF, SCHED_FUSED2, SCHED_AUTO = 0, 1, 2, 3, 4
 FLAG_GRAPH = 1
 FLAG_TVL1 = 2
+FLAG_LEAVE_OPEN = 4
 NOALLOC_MAX_BYTES = 64 << 20  # TGV_NOALLOC_MAX_BYTES
 MODEL_PINHOLE, MODEL_SCAN360 = 0, 1
 HIST_ACCUMULATE = 1
@@ -514,15 +515,14 @@ class State:
     def reset(self, u0: torch.Tensor, stream=None):
         self.ctx._check(self.ctx.lib.tgv_state_reset(self.ctx.h, self.h, _ptr(u0), _stream(stream)))
 
-    def export(self, stream=None) -> dict:
+    def export(self, stream=None, fields=("u", "v", "u_prev", "v_prev", "p", "q")) -> dict:
         dev = torch.device("cuda", self.ctx.device)
         n = self.n
-        out = dict(u=torch.empty(n, device=dev), v=torch.empty(3 * n, device=dev),
-                   u_prev=torch.empty(n, device=dev), v_prev=torch.empty(3 * n, device=dev),
-                   p=torch.empty(3 * n, device=dev), q=torch.empty(6 * n, device=dev))
-        self.ctx._check(self.ctx.lib.tgv_state_export(self.ctx.h, self.h, _ptr(out["u"]), _ptr(out["v"]),
-                                                      _ptr(out["u_prev"]), _ptr(out["v_prev"]), _ptr(out["p"]),
-                                                      _ptr(out["q"]), _stream(stream)))
+        size = dict(u=n, v=3 * n, u_prev=n, v_prev=3 * n, p=3 * n, q=6 * n)
+        out = {f: torch.empty(size[f], device=dev) for f in fields}
+        self.ctx._check(self.ctx.lib.tgv_state_export(self.ctx.h, self.h, _ptr(out.get("u")), _ptr(out.get("v")),
+                                                      _ptr(out.get("u_prev")), _ptr(out.get("v_prev")),
+                                                      _ptr(out.get("p")), _ptr(out.get("q")), _stream(stream)))
         return out
 
     def import_(self, f: dict, iters_done: int = 0, stream=None):

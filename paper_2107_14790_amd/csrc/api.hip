@@ -72,7 +72,7 @@ bool params_ok(const tgv_params *p) {
     if (p->storage < 0 || p->storage > 2) return false;
     if (p->schedule < TGV_SCHED_FUSED || p->schedule > TGV_SCHED_AUTO) return false;
     if (p->tile_y < 0 || p->tile_z < 0) return false;
-    if (p->flags & ~(TGV_FLAG_GRAPH | TGV_FLAG_TVL1)) return false;
+    if (p->flags & ~(TGV_FLAG_GRAPH | TGV_FLAG_TVL1 | TGV_FLAG_LEAVE_OPEN)) return false;
     if (p->tile_y != 0) {
         const int cz = p->tile_z > 0 ? p->tile_z : 1;
         if (p->schedule == TGV_SCHED_FUSED2 ? !tiled2_shape_ok(p->tile_y, cz) : !tiled_shape_ok(p->tile_y, cz))
@@ -496,6 +496,8 @@ static void state_layout(tgv_state *st) {
     st->xc = 0;
     st->yc = 0;
     st->fresh = true;
+    st->open = false;
+    st->open_tvl1 = 0;
     st->iters_done = 0;
 }
 
@@ -560,6 +562,7 @@ extern "C" tgv_status tgv_state_reset(tgv_ctx *ctx, tgv_state *st, const float *
     launch_fill_bytes0(st->p[0], 3 * n * sb, S(stream));
     launch_fill_bytes0(st->q[0], 6 * n * sb, S(stream));
     st->fresh = true;
+    st->open = false;
     st->iters_done = 0;
     return check_launch(ctx, "state reset");
 }
@@ -568,6 +571,7 @@ extern "C" tgv_status tgv_state_export(tgv_ctx *ctx, const tgv_state *st, float 
                                        float *v_prev, float *p, float *q, void *stream) {
     if (!ctx) return TGV_E_INVAL;
     if (!st) return fail(ctx, TGV_E_INVAL, "tgv_state_export: null state");
+    if (st->open) return fail(ctx, TGV_E_INVAL, "tgv_state_export: the state is open (close it with a solve)");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     long long n = st->n;
     int xp = st->fresh ? st->xc : (st->xc ^ 1);
@@ -591,6 +595,7 @@ extern "C" tgv_status tgv_state_import(tgv_ctx *ctx, tgv_state *st, const float 
     st->xc = 0;
     st->yc = 0;
     st->fresh = false;
+    st->open = false;
     HIP_TRY(ctx, hipMemcpyAsync(st->u[0], u, 4 * n, hipMemcpyDeviceToDevice, S(stream)));
     HIP_TRY(ctx, hipMemcpyAsync(st->u[1], u_prev, 4 * n, hipMemcpyDeviceToDevice, S(stream)));
     launch_convert(v, 0, st->v[0], st->storage, 3 * n, S(stream));
@@ -621,6 +626,7 @@ static bool same_grid(const tgv_grid &a, const tgv_grid &b) {
 
 static tgv_status run_energy(tgv_ctx *ctx, const tgv_state *st, const uint16_t *hist, const tgv_bins *bins,
                              const tgv_params *params, tgv_stats *out, hipStream_t s) {
+    if (st->open) return fail(ctx, TGV_E_INVAL, "energy: the state is open (close it with a solve)");
     Dims d = make_dims(st->grid);
     Coef cf = make_coef(*params, *bins);
     int np = energy_partials(d);
@@ -658,71 +664,85 @@ extern "C" tgv_status tgv_energy(tgv_ctx *ctx, const tgv_state *st, const uint16
     return run_energy(ctx, st, hist, bins, params, stats_host, S(stream));
 }
 
-// params->iters iterations on a state (kernels only: nothing is allocated)
+// params->iters iterations on a state (kernels only: nothing is allocated).
+// A closed state starts with its opening dual step (the first iteration's
+// dual half); each fused pass then completes one iteration's primal half
+// and the next one's dual half; the closing primal step completes the last
+// iteration unless TGV_FLAG_LEAVE_OPEN keeps the state open for the next
+// call, which then starts with a fused pass.
 static tgv_status advance(tgv_ctx *ctx, tgv_state *st, const uint16_t *hist, const tgv_bins *bins,
                           const tgv_params *params, hipStream_t s) {
     Dims d = make_dims(st->grid);
     Coef cf = make_coef(*params, *bins);
-    int N = params->iters;
-    if (N > 0) {
+    const int N = params->iters;
+    const bool leave_open = (params->flags & TGV_FLAG_LEAVE_OPEN) != 0;
+    if (st->open && cf.tvl1 != st->open_tvl1)
+        return fail(ctx, TGV_E_INVAL, "solve: an open state continues with the model it was opened with");
+    if (!st->open && N == 0) return TGV_OK;
+    int F = N;  // fused passes
+    if (!st->open) {
         if (cf.tvl1) zero_vq(st, s);
-        // dual step from (x^n, x^{n-1}, y^n): y^{n+1}, in place
-        {
-            SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
-            if (st->fresh) {
-                b.xo_u = b.xc_u;
-                b.xo_v = b.xc_v;
-            }
-            launch_ref(KIND_DUAL, st->storage, b, d, cf, s);
+        // opening dual step from (x^n, x^{n-1}, y^n): y^{n+1}, in place
+        SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
+        if (st->fresh) {
+            b.xo_u = b.xc_u;
+            b.xo_v = b.xc_v;
         }
-        // AUTO: two iterations per pass unless the block is small (measured
-        // crossover near 96^3 in float32 and 16-bit storage: 48 MiB per iteration)
-        int sched = params->schedule;
-        if (sched == TGV_SCHED_AUTO) {
-            const long long per_voxel = st->storage == 0 ? 120 : 72;
-            sched = (params->tile_y == 0 && d.n * per_voxel > (48LL << 20)) ? TGV_SCHED_FUSED2 : TGV_SCHED_FUSED;
+        launch_ref(KIND_DUAL, st->storage, b, d, cf, s);
+        st->open = true;
+        st->open_tvl1 = cf.tvl1;
+        st->fresh = false;
+        F = N - 1;
+    }
+    // AUTO: two iterations per pass unless the block is small (measured
+    // crossover near 96^3 in float32 and 16-bit storage: 48 MiB per iteration)
+    int sched = params->schedule;
+    if (sched == TGV_SCHED_AUTO) {
+        const long long per_voxel = st->storage == 0 ? 120 : 72;
+        sched = (params->tile_y == 0 && d.n * per_voxel > (48LL << 20)) ? TGV_SCHED_FUSED2 : TGV_SCHED_FUSED;
+    }
+    if (sched == TGV_SCHED_SPLIT) {
+        // a fused pass as its two per-voxel kernels
+        for (int it = 0; it < F; it++) {
+            launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
+            st->xc ^= 1;
+            launch_ref(KIND_DUAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
         }
-        if (sched == TGV_SCHED_SPLIT) {
-            for (int it = 0; it < N; it++) {
-                if (it > 0) launch_ref(KIND_DUAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
-                launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
-                st->xc ^= 1;
-            }
-        } else {
-            int ty = params->tile_y ? params->tile_y : default_tile_y(st->storage, d);
-            int cz = params->tile_z ? params->tile_z
-                                    : choose_tile_z(d, ty, ctx->cus * tiled_blocks_per_cu(st->storage, ty, d));
-            int it = 0;
-            if (sched == TGV_SCHED_FUSED2 && tiled_fits(d)) {
-                // pairs of fused iterations in one pass; x^{n+1} is never
-                // written, which only the final primal pass could notice,
-                // and it overwrites that buffer
-                const int ty2 = params->tile_y ? params->tile_y : DEFAULT_TILE2_Y;
-                const int cz2 = params->tile_z ? params->tile_z
-                                               : choose_tile2_z(d, ty2, ctx->cus * tiled2_blocks_per_cu(st->storage, ty2));
-                for (; it + 2 < N; it += 2) {
-                    launch_tiled2(st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, ty2, cz2, s);
-                    st->xc ^= 1;
-                    st->yc ^= 1;
-                }
-                ty = default_tile_y(st->storage, d);
-                if (!params->tile_z) cz = choose_tile_z(d, ty, ctx->cus * tiled_blocks_per_cu(st->storage, ty, d));
-            }
-            for (; it + 1 < N; it++) {
-                SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
-                if (sched == TGV_SCHED_FUSED_REF) launch_ref(KIND_FUSED, st->storage, b, d, cf, s);
-                else launch_tiled(st->storage, b, d, cf, ty, cz, s);
+    } else if (F > 0) {
+        int ty = params->tile_y ? params->tile_y : default_tile_y(st->storage, d);
+        int cz = params->tile_z ? params->tile_z
+                                : choose_tile_z(d, ty, ctx->cus * tiled_blocks_per_cu(st->storage, ty, d));
+        int it = 0;
+        if (sched == TGV_SCHED_FUSED2 && tiled_fits(d)) {
+            // pairs of fused passes in one sweep; x^{n+1} is never written,
+            // which only the closing primal pass could notice, and it
+            // overwrites that buffer
+            const int ty2 = params->tile_y ? params->tile_y : DEFAULT_TILE2_Y;
+            const int cz2 = params->tile_z ? params->tile_z
+                                           : choose_tile2_z(d, ty2, ctx->cus * tiled2_blocks_per_cu(st->storage, ty2));
+            for (; it + 2 <= F; it += 2) {
+                launch_tiled2(st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, ty2, cz2, s);
                 st->xc ^= 1;
                 st->yc ^= 1;
             }
-            launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
-            st->xc ^= 1;
+            ty = default_tile_y(st->storage, d);
+            if (!params->tile_z) cz = choose_tile_z(d, ty, ctx->cus * tiled_blocks_per_cu(st->storage, ty, d));
         }
-        st->fresh = false;
-        st->iters_done += N;
-        return check_launch(ctx, "solve");
+        for (; it < F; it++) {
+            SolveBufs b = bufs_of(st, st->xc, st->yc, hist);
+            if (sched == TGV_SCHED_FUSED_REF) launch_ref(KIND_FUSED, st->storage, b, d, cf, s);
+            else launch_tiled(st->storage, b, d, cf, ty, cz, s);
+            st->xc ^= 1;
+            st->yc ^= 1;
+        }
     }
-    return TGV_OK;
+    if (!leave_open) {
+        launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist), d, cf, s);
+        st->xc ^= 1;
+        st->open = false;
+    }
+    st->iters_done += N;
+    return check_launch(ctx, "solve");
 }
 
 extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t *hist, const tgv_bins *bins,
@@ -734,6 +754,8 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
     if (!params_ok(params)) return fail(ctx, TGV_E_INVAL, "tgv_solve: bad params");
     if (!hist) return fail(ctx, TGV_E_INVAL, "tgv_solve: null hist");
     if (!state && !u_io) return fail(ctx, TGV_E_INVAL, "tgv_solve: fresh solve needs u_io");
+    if ((params->flags & TGV_FLAG_LEAVE_OPEN) && (!state || u_io || stats_host))
+        return fail(ctx, TGV_E_INVAL, "tgv_solve: TGV_FLAG_LEAVE_OPEN needs a state and no u_io or statistics");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = S(stream);
     tgv_state *st = state;
@@ -772,6 +794,7 @@ extern "C" tgv_status tgv_solve(tgv_ctx *ctx, const tgv_grid *grid, const uint16
 // 256-byte aligned): kernels and device copies only, nothing allocated.
 static tgv_status fresh_solve_on(tgv_ctx *ctx, void *mem, const tgv_grid *grid, const uint16_t *hist,
                                  const tgv_bins *bins, const tgv_params *params, float *u_io, hipStream_t s) {
+    if (params->flags & TGV_FLAG_LEAVE_OPEN) return fail(ctx, TGV_E_INVAL, "fresh solve: TGV_FLAG_LEAVE_OPEN");
     tgv_state st{};
     st.grid = *grid;
     st.storage = params->storage;
@@ -861,17 +884,43 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
     const int ty = params->tile_y ? params->tile_y : (two ? DEFAULT_TILE2_Y : DEFAULT_BATCH_TILE_Y);
     if (two ? !tiled2_shape_ok(ty, 1) : !tiled_shape_ok(ty, 1))
         return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: tile_y %d", ty);
+    const bool leave_open = (params->flags & TGV_FLAG_LEAVE_OPEN) != 0;
+    if (leave_open && stats_host)
+        return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: TGV_FLAG_LEAVE_OPEN with statistics");
+    for (int i = 0; i < n; i++)
+        if (states[i]->open && states[i]->open_tvl1 != cf.tvl1)
+            return fail(ctx, TGV_E_INVAL, "tgv_solve_batch: open state %d continues with the model it was opened with", i);
     if (n == 0 || N == 0) {
+        // nothing to advance: close the open states unless they stay open
+        for (int i = 0; i < n && !leave_open; i++) {
+            tgv_state *st = states[i];
+            if (!st->open) continue;
+            launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist[i]), make_dims(st->grid), cf, s);
+            st->xc ^= 1;
+            st->open = false;
+        }
+        tgv_status r = check_launch(ctx, "batched solve");
+        if (r != TGV_OK) return r;
         if (stats_host)
             for (int i = 0; i < n; i++) {
-                tgv_status r = run_energy(ctx, states[i], hist[i], bins, params, &stats_host[i], s);
+                r = run_energy(ctx, states[i], hist[i], bins, params, &stats_host[i], s);
                 if (r != TGV_OK) return r;
             }
         return TGV_OK;
     }
-    // 1. dual step of every block (in place)
+    // 1. opening dual step of every closed block (in place).  A block that
+    //    came open needs N fused passes, one opened here N - 1: with both
+    //    kinds in the batch, the blocks that came open take one extra
+    //    batched pass first, over the head of the tile table (they are
+    //    listed first)
+    std::vector<char> came_open(n, 0);
+    bool any_open = false, any_closed = false;
     for (int i = 0; i < n; i++) {
         tgv_state *st = states[i];
+        came_open[i] = st->open ? 1 : 0;
+        any_open |= st->open;
+        any_closed |= !st->open;
+        if (st->open) continue;
         if (cf.tvl1) zero_vq(st, s);
         SolveBufs b = bufs_of(st, st->xc, st->yc, hist[i]);
         if (st->fresh) {
@@ -879,11 +928,20 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             b.xo_v = b.xc_v;
         }
         launch_ref(KIND_DUAL, st->storage, b, make_dims(st->grid), cf, s);
+        st->open = true;
+        st->open_tvl1 = cf.tvl1;
+        st->fresh = false;
     }
+    const bool extra = any_open && any_closed;
+    // blocks in table order: those that came open first
+    std::vector<int> order;
+    for (int pass = 0; pass < 2; pass++)
+        for (int i = 0; i < n; i++)
+            if ((came_open[i] != 0) == (pass == 0)) order.push_back(i);
     // 2. block and tile tables (blocks too large for 32-bit tile offsets run alone)
     std::vector<int> big;
     HIP_TRY(ctx, hipEventSynchronize(ctx->bt_evt));  // the previous upload has left the staging buffers
-    int nb = 0, nt = 0;
+    int nb = 0, nt = 0, nt_extra = 0;
     {
         long long tiles = 0;
         for (int i = 0; i < n; i++) {
@@ -922,7 +980,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             HIP_TRY(ctx, hipHostMalloc((void **)&ctx->bt_tiles_host, sizeof(int4) * tiles, hipHostMallocDefault));
             ctx->bt_tiles_cap = (int)tiles;
         }
-        for (int i = 0; i < n; i++) {
+        for (int i : order) {
             tgv_state *st = states[i];
             Dims d = make_dims(st->grid);
             if (!tiled_fits(d)) {
@@ -940,13 +998,17 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             bb.hist = hist[i];
             bb.d = d;
             bb.cz = cz;
-            bb.xc = st->xc;
-            bb.yc = st->yc;
+            // parity seen by the common passes: after the extra pass for a
+            // block that came open (which runs with flip 1)
+            const int pre = (extra && came_open[i]) ? 1 : 0;
+            bb.xc = st->xc ^ pre;
+            bb.yc = st->yc ^ pre;
             bb.pad = 0;
             int ntx = (d.nx + 63) / 64, nty = (d.ny + ty - 1) / ty, ntz = (d.nz + cz - 1) / cz;
             for (int z = 0; z < ntz; z++)
                 for (int y = 0; y < nty; y++)
                     for (int x = 0; x < ntx; x++) ctx->bt_tiles_host[nt++] = make_int4(nb, x | (y << 16), z, 0);
+            if (extra && came_open[i]) nt_extra = nt;
             nb++;
         }
     }
@@ -958,9 +1020,19 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
         HIP_TRY(ctx, hipMemcpyAsync(ctx->bt_tiles_dev, ctx->bt_tiles_host, sizeof(int4) * nt, hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipEventRecord(ctx->bt_evt, s));
     }
-    // 3. N-1 fused iterations of all blocks: one persistent launch each
+    // 3. fused passes of all blocks: N - 1 after an opening dual step, N
+    //    when every block came open; first the extra pass of the blocks
+    //    that came open in a mixed batch (one-iteration batched launch over
+    //    their tiles)
+    if (extra && nt_extra > 0) {
+        int g1 = ctx->cus * batch_blocks_per_cu(params->storage, ty);
+        g1 = (g1 + 7) / 8 * 8;
+        const int cap = (nt_extra + 7) / 8 * 8;
+        launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt_extra, ctx->counters,
+                     cf, ty, 1, g1 < cap ? g1 : cap, s);
+    }
     const int grid = persistent_grid(ctx, params->storage, ty, nt, two);
-    const int F = N - 1;
+    const int F = any_closed ? N - 1 : N;
     // batched launches: F one-iteration passes, or F/2 two-iteration passes
     // (plus, for an odd F, one one-iteration pass per block after them)
     const int LB = two ? F / 2 : F;
@@ -1029,21 +1101,25 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
         tgv_state *st = states[i];
         Dims d = make_dims(st->grid);
         int xc = st->xc, yc = st->yc;
-        for (int it = 0; it < F; it++) {
+        const int Fi = F + ((extra && came_open[i]) ? 1 : 0);
+        for (int it = 0; it < Fi; it++) {
             launch_ref(KIND_FUSED, st->storage, bufs_of(st, xc, yc, hist[i]), d, cf, s);
             xc ^= 1;
             yc ^= 1;
         }
     }
     // 4. parities after the fused passes, then the closing primal step
+    //    unless the states stay open
     for (int i = 0; i < n; i++) {
         tgv_state *st = states[i];
-        const int flips = tiled_fits(make_dims(st->grid)) ? tiled_flips : F;
+        const int flips = (tiled_fits(make_dims(st->grid)) ? tiled_flips : F) + ((extra && came_open[i]) ? 1 : 0);
         st->xc ^= (flips & 1);
         st->yc ^= (flips & 1);
-        launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist[i]), make_dims(st->grid), cf, s);
-        st->xc ^= 1;
-        st->fresh = false;
+        if (!leave_open) {
+            launch_ref(KIND_PRIMAL, st->storage, bufs_of(st, st->xc, st->yc, hist[i]), make_dims(st->grid), cf, s);
+            st->xc ^= 1;
+            st->open = false;
+        }
         st->iters_done += N;
     }
     tgv_status r = check_launch(ctx, "batched solve");

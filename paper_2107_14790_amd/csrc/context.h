@@ -59,5 +59,7 @@ struct tgv_state {
     void *q[2];
     int xc, yc;             // current primal and dual buffer
     bool fresh;             // previous iterate == current (no step taken yet)
+    bool open;              // the last iteration's dual half is done, its primal half pending
+    int open_tvl1;          // the model the state was opened with
     int64_t iters_done;
 };
