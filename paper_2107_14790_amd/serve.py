@@ -3,13 +3,17 @@
 Blocks (octree leaves, Sec. 4.3-4.5) arrive as requests.  The server keeps
 every admitted block's state resident in HBM and advances all active blocks
 together, a few iterations per tick, with one batched solve call (one
-persistent launch per iteration over all their tiles).  Between ticks it
-retires finished blocks (freeing their memory) and admits waiting ones in
-arrival order as the memory budget allows; the histograms of newly admitted
-blocks are built on a side stream while the current tick runs on the
-device.  Because a solve resumed from its state is bit-identical to an
-uninterrupted one, and a batched solve is bit-identical to a solo one, a
-served block's result does not depend on what else was in flight.
+persistent launch per iteration, or pair of iterations, over all their
+tiles).  Between ticks it retires finished blocks (freeing their memory)
+and admits waiting ones in arrival order as the memory budget allows; the
+histograms of newly admitted blocks are built on a side stream while the
+current tick runs on the device.  Ticks are issued ahead: the host queues
+the next tick while the device still runs the current one (at most `depth`
+ticks in flight) and learns that a tick has ended from an event, so the
+device does not wait for the host between ticks.  Because a solve resumed
+from its state is bit-identical to an uninterrupted one, and a batched
+solve is bit-identical to a solo one, a served block's result does not
+depend on what else was in flight.
 
 The scheduling logic talks to a backend (GPU backend below; tests use a
 host-only fake), so it is testable without a GPU.
@@ -61,16 +65,21 @@ class Server:
     """Continuous-batching server.
 
     backend must provide: nbytes(grid) -> int, prepare(request) -> handle
-    (may raise), step(handles, k) -> None (launch, may return before the
-    device finishes), sync() -> None, finish(handle) -> output, release(handle).
+    (may raise), step(handles, k) -> None (queue k iterations; returns before
+    the device finishes), finish(handle) -> output (queued after the steps),
+    release(handle) (the handle's memory may be reused by work queued later),
+    mark() -> token (marks the work queued so far) and done(token) -> bool.
     """
 
     def __init__(self, backend, budget_bytes: int, tick_iters: int = 50, max_active: int = 1 << 30,
-                 clock: Callable[[], float] = None, sleep: Callable[[float], None] = None):
+                 clock: Callable[[], float] = None, sleep: Callable[[float], None] = None, depth: int = 2,
+                 poll_s: float = 1e-4):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.tick_iters = int(tick_iters)
         self.max_active = int(max_active)
+        self.depth = max(1, int(depth))
+        self.poll_s = float(poll_s)
         self._clock = clock or time.perf_counter
         self._sleep = sleep or time.sleep
         self.used = 0
@@ -138,9 +147,32 @@ class Server:
                 pending.append(reqs[nxt])
                 nxt += 1
 
+        # ticks queued on the device and not yet seen to end: (token, jobs
+        # whose last iterations they hold)
+        inflight: deque = deque()
+
+        def retire_done(block: bool):
+            """Stamp the jobs of the ticks that have ended; with block, wait
+            (taking arrivals meanwhile) until the oldest has ended."""
+            while inflight:
+                tok, jobs = inflight[0]
+                if not self.backend.done(tok):
+                    if not block:
+                        return
+                    arrivals()
+                    admit()
+                    self._sleep(self.poll_s)
+                    continue
+                inflight.popleft()
+                t = now()
+                for j in jobs:
+                    j.result.finished = t
+                block = False
+
         while True:
             arrivals()
             admit()
+            retire_done(False)
             # cancelled active jobs leave at the tick boundary
             for j in [j for j in active if j.req.cancelled]:
                 active.remove(j)
@@ -150,6 +182,9 @@ class Server:
                 j.result.error = "cancelled"
                 j.result.finished = now()
             if not active:
+                if inflight:
+                    retire_done(True)
+                    continue
                 if nxt >= len(reqs) and not pending:
                     break
                 if pending and nxt >= len(reqs) and self.used == 0:
@@ -177,25 +212,33 @@ class Server:
                     j.result.finished = now()
                 active = [j for j in active if j not in running]
                 continue
-            # while the device works: take in and prepare new arrivals (they
-            # join the next tick)
-            arrivals()
-            admit()
-            self.backend.sync()
             self.ticks += 1
+            # the iteration counts are known on the host: blocks whose last
+            # iterations this tick holds are finished and released now (their
+            # results and memory reuse are ordered after the tick on the
+            # device); they count as done when the tick is seen to end
             ran = set(id(j) for j in running)
-            keep = []
+            keep, ended = [], []
             for j in active:
                 if id(j) in ran:
                     j.remaining -= k
                 if j.remaining <= 0:
                     j.result.output = self.backend.finish(j.handle)
-                    j.result.finished = now()
                     self.backend.release(j.handle)
                     self.used -= j.nbytes
+                    ended.append(j)
                 else:
                     keep.append(j)
             active = keep
+            inflight.append((self.backend.mark(), ended))
+            # while the device works: take in and prepare new arrivals (they
+            # join the next tick); wait only when `depth` ticks are queued
+            arrivals()
+            admit()
+            retire_done(len(inflight) >= self.depth)
+        retire_done(True)
+        while inflight:
+            retire_done(True)
         return [results[r.rid] for r in reqs]
 
 
@@ -214,9 +257,12 @@ class GpuBackend:
     prepare() builds the block's histograms from resident pyramids and
     initialises its state on a side stream (overlapping the tick in flight
     on the main stream); step() issues one batched solve of k iterations of
-    all given blocks on the main stream after waiting for their
-    preparation; states live in torch-allocated memory, so retiring a block
-    never synchronises the device."""
+    all given blocks on the main stream after waiting for their preparation
+    and leaves the states open (the last iteration's primal half pending),
+    so the next tick's first pass completes it fused with its own first
+    dual half and a tick has no per-block opening or closing kernels;
+    finish() closes the state and exports u; states live in torch-allocated
+    memory, so retiring a block never synchronises the device."""
 
     def __init__(self, ctx, pyr, W: int, H: int, cams, bins=None, params=None, tile_z_of=None, keep_outputs=True):
         import torch
@@ -267,16 +313,28 @@ class GpuBackend:
             if h["event"] is not None:
                 self.main.wait_event(h["event"])
                 h["event"] = None
-        p = dataclasses.replace(self.params, iters=int(k))
+        p = dataclasses.replace(self.params, iters=int(k), flags=self.params.flags | self.tgv.FLAG_LEAVE_OPEN)
         self.ctx.solve_batch([h["state"] for h in handles], [h["hist"] for h in handles], p, self.bins,
                              tile_z=[h["tile_z"] or 32 for h in handles], stream=self.main)
 
-    def sync(self):
-        self.main.synchronize()
+    def mark(self):
+        ev = self.torch.cuda.Event()
+        ev.record(self.main)
+        return ev
+
+    def done(self, token) -> bool:
+        return token is None or token.query()
 
     def finish(self, h):
-        u = h["state"].export(stream=self.main)["u"]
-        return u if self.keep_outputs else float(u.double().sum().item())
+        """Close the state (its last primal half) and export u; with
+        keep_outputs False a float64 checksum of u (a device scalar)."""
+        p = dataclasses.replace(self.params, iters=0)
+        self.ctx.solve(h["grid"], h["hist"], None, p, self.bins, state=h["state"], stream=self.main)
+        u = h["state"].export(stream=self.main, fields=("u",))["u"]
+        if self.keep_outputs:
+            return u
+        with self.torch.cuda.stream(self.main):
+            return u.double().sum()
 
     def release(self, h):
         h["state"].close()

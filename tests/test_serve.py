@@ -59,8 +59,11 @@ class FakeBackend:
             h["done"] += k
         self.clock.t += self.c * k * sum(h["n"] for h in handles)
 
-    def sync(self):
-        pass
+    def mark(self):
+        return None  # the work is done when step returns
+
+    def done(self, token):
+        return True
 
     def finish(self, h):
         return (h["rid"], h["n"], h["done"])
@@ -163,3 +166,59 @@ def test_failed_tick_fails_its_blocks_and_server_continues():
     assert failed and all("step failed" in r.error for r in failed)
     assert by[50].ok and by[50].output[2] == 100
     assert srv.used == 0
+
+
+class AsyncFakeBackend(FakeBackend):
+    """A device that runs queued ticks one after another while the host goes
+    on: step costs the host `host_cost` and queues the tick's service time on
+    the device; a token is the device time at which the work queued so far
+    ends."""
+
+    def __init__(self, clock, host_cost=1e-3, **kw):
+        super().__init__(clock, **kw)
+        self.host_cost = host_cost
+        self.dev_t = 0.0
+        self.busy = 0.0
+        self.first_start = None
+        self.queued = []  # device end times of queued ticks
+
+    def step(self, handles, k):
+        self.ticks += 1
+        self.clock.t += self.host_cost
+        svc = self.c * k * sum(h["n"] for h in handles)
+        start = max(self.dev_t, self.clock.t)
+        if self.first_start is None:
+            self.first_start = start
+        self.dev_t = start + svc
+        self.busy += svc
+        for h in handles:
+            h["done"] += k
+        self.queued = [t for t in self.queued if t > self.clock.t] + [self.dev_t]
+        self.max_queued = max(getattr(self, "max_queued", 0), len(self.queued))
+
+    def mark(self):
+        return self.dev_t
+
+    def done(self, token):
+        return self.clock.t >= token
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_ticks_are_queued_ahead_of_the_device(depth):
+    rq = [Request(i, G((48, 48, 48)), 0.0, 500) for i in range(8)]
+    clk = VClock()
+    be = AsyncFakeBackend(clk, host_cost=2e-3, per_voxel_iter=1e-9)
+    srv = Server(be, 10 ** 12, tick_iters=50, clock=clk, sleep=clk.sleep, depth=depth, poll_s=1e-5)
+    res = srv.run(rq)
+    assert all(r.ok and r.output[2] == 500 for r in res)
+    assert be.max_queued <= depth
+    idle = (be.dev_t - be.first_start) - be.busy
+    if depth == 1:
+        # the device waits for the host between ticks
+        assert idle >= 0.9 * (srv.ticks - 1) * be.host_cost
+    else:
+        # the next tick is already queued when one ends
+        assert idle <= 1e-9
+    # a block counts as done only once its last tick has ended on the device
+    assert all(r.finished >= be.first_start + 500 * 48 ** 3 * 8 * 1e-9 - 1e-9 for r in res)
+    assert be.active == 0 and srv.used == 0
