@@ -95,6 +95,21 @@ def measured_traffic(storage: int, tile: str, kernel: str = "fused"):
     return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
 
 
+def hist_valu_instructions():
+    """VALU wave-instructions of one histogram launch on the terrain256
+    workload, from the committed counter summary, or None if the kernel's
+    source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_hist_terrain256_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    with open(os.path.join(ROOT, "paper_2107_14790_amd/csrc/pyramid_hist.hip"), "rb") as fh:
+        h = hashlib.sha256(fh.read()).hexdigest()
+    return t["SQ_INSTS_VALU"] if t.get("kernel_source_sha256") == h else None
+
+
 def cpu_baseline(scene, bins_centers, iters_sample: int = 150, crop: int = 64, nvox_hist: int = 20000):
     """The oracle timed on a bounded sample of the workload (single thread)."""
     import oracle
@@ -254,9 +269,17 @@ def bench_block(args):
     torch.cuda.synchronize()
     pyr_ms, hist_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     pairs = nvox * len(sc.cams)  # voxel x camera pairs before the cull
-    # ceiling: ~60 float32 lane-operations per pair at 3.93e13 non-packed lane-ops/s
-    hist_rate = dict(pairs=pairs, ms=hist_ms, pairs_per_s=pairs / (hist_ms * 1e-3),
-                     frac_of_valu_ceiling=round(pairs / (hist_ms * 1e-3) / (3.93e13 / 60), 3))
+    # VALU ceiling of the histogram kernel: its measured VALU instructions
+    # (SQ_INSTS_VALU of this workload's launch, committed counter summary)
+    # issued at one wave64 instruction per SIMD per two cycles (the 157.3
+    # TFLOP/s FP32 vector peak: 32 lanes per SIMD per cycle) on 1024 SIMDs
+    hist_rate = dict(pairs=pairs, ms=hist_ms, pairs_per_s=pairs / (hist_ms * 1e-3))
+    vi = hist_valu_instructions() if n == 256 and len(sc.cams) == 64 else None
+    if vi is not None:
+        floor_ms = vi / (1024 * 2.4e9 * 0.5) * 1e3
+        hist_rate.update(valu_wave_instructions=vi, lane_instructions_per_pair=round(vi * 64 / pairs, 1),
+                         valu_floor_ms=round(floor_ms, 4), frac_of_valu_ceiling=round(floor_ms / hist_ms, 3),
+                         valu_source="profiles/k_hist_terrain256_counters.md (SQ_INSTS_VALU)")
     def kernel_roofline(schedule):
         """Average launch time of the schedule's dominant kernel (HIP events on
         the library's stream: median difference of 400- and 200-iteration
@@ -610,7 +633,7 @@ def bench_city_serve(args):
     mix_reqs = [Request(i, pool[i], 0.0, iters) for i in range(6)]
     mix = Server(be, budget, tick_iters=50).run(mix_reqs)
     alone = [Server(be, budget, tick_iters=50).run([Request(0, pool[i], 0.0, iters)])[0] for i in range(6)]
-    same = all(a.output == m.output for a, m in zip(alone, mix))
+    same = all(float(a.output) == float(m.output) for a, m in zip(alone, mix))
     out = {
         "metric": METRIC,
         "value": hot["updates_per_s_interior"],
