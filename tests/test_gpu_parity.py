@@ -284,16 +284,49 @@ def test_zero_iterations_and_alpha_zero_median(ctx):
     assert np.array_equal(u, np.float32(med).astype(np.float64))
 
 
-@pytest.mark.parametrize("storage", [1, 2])
-def test_half_storage_close_to_oracle(ctx, storage):
-    say("half storage", storage)
+# unit roundoff of the storage format of v, p, q (FP16: 11-bit significand,
+# BF16: 8-bit)
+UNIT_ROUNDOFF = {1: 2.0 ** -11, 2: 2.0 ** -8}
+
+
+def zero_crossings(u, ref):
+    """Crossing positions t = u_a / (u_a - u_b) on the grid edges where both
+    fields change sign (in voxels): |t - t_ref| per such edge."""
+    a, b = u.reshape(32, 32, 32), ref.reshape(32, 32, 32)
+    out = []
+    for ax in range(3):
+        a0, a1 = np.moveaxis(a, ax, 0)[:-1], np.moveaxis(a, ax, 0)[1:]
+        b0, b1 = np.moveaxis(b, ax, 0)[:-1], np.moveaxis(b, ax, 0)[1:]
+        both = ((a0 > 0) != (a1 > 0)) & ((b0 > 0) != (b1 > 0))
+        out.append(np.abs(a0[both] / (a0[both] - a1[both]) - b0[both] / (b0[both] - b1[both])))
+    return np.concatenate(out)
+
+
+def test_half_storage_close_to_oracle(ctx):
+    """16-bit storage of v, p, q against the float64 oracle after 300
+    iterations on the sphere block.  The deviation is a storage rounding
+    effect: in units of each format's unit roundoff u_s (FP16 2^-11, BF16
+    2^-8) it stays within the stated bounds, max |u - u_64| <= 128 u_s,
+    mean |u - u_64| <= u_s and a mean zero-crossing shift <= 8 u_s voxel,
+    and BF16's mean deviation is 2 to 32 times FP16's, as the ratio of their
+    unit roundoffs (8) predicts for rounding, not for a defect of one path."""
     sc = scenes.sphere_scene()
     ref_h, _ = oracle.histograms(sc)
-    u16, s = solve_gpu(ctx, ref_h, (32, 32, 32), 300, storage=storage, stats=True)
     st = oracle.solve(ref_h, (32, 32, 32), scenes.default_bins(), 300)
-    err = np.abs(u16 - st.u).max()
-    say("storage", storage, "max err", err)
-    assert err < 0.05 and s["nonfinite"] == 0
+    mean = {}
+    for storage in (1, 2):
+        say("half storage", storage)
+        u16, s = solve_gpu(ctx, ref_h, (32, 32, 32), 300, storage=storage, stats=True)
+        us = UNIT_ROUNDOFF[storage]
+        d = np.abs(u16 - st.u)
+        zc = zero_crossings(u16.astype(np.float64), st.u)
+        say("storage", storage, "max", d.max() / us, "mean", d.mean() / us, "zc mean", zc.mean() / us, "u_s")
+        assert s["nonfinite"] == 0 and zc.size > 1000
+        assert d.max() <= 128 * us
+        assert d.mean() <= us
+        assert zc.mean() <= 8 * us
+        mean[storage] = d.mean()
+    assert 2.0 <= mean[2] / mean[1] <= 32.0
 
 
 # ---------------------------------------------------------------------------
