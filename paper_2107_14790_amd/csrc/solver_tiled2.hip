@@ -11,7 +11,8 @@
 // iterations.  Stage B needs stage A's results on the tile plus the first
 // ring, stage A needs the state on the tile plus two rings; the rings are
 // carried by five extra waves (two row waves per ring and one for the
-// columns and corners).  Both stages use the per-voxel arithmetic of the
+// columns and corners).  Stage B takes each plane's histograms from LDS,
+// where stage A left them two steps earlier.  Both stages use the per-voxel arithmetic of the
 // one-iteration kernels, so two iterations here are bit-identical to two
 // iterations there.
 #include "fields.h"
@@ -128,6 +129,13 @@ struct XLds {
     float sV[3 * NE];
 };
 
+// histograms of the last three planes of stage A, for stage B (each lane
+// reads back what it wrote two steps earlier)
+template <int TY>
+struct HLds {
+    uint4 h[3][64 * (TY + 5)];
+};
+
 // One stage of one column: the z-pipeline of the one-iteration kernel,
 // with its inputs handed in per plane and its dual results handed out.
 struct Stage {
@@ -146,8 +154,8 @@ struct Stage {
 // skipped load reads 0) nor stored.  Other TV-L1 solves run the TV = false
 // kernels, which read and write those zeros.
 template <int STORE, int TY, int SCP, bool TV = false, bool UNI = false>
-__device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf<STORE> &Xc, const YBuf<STORE> &Yc,
-                                          const XBuf<STORE> &Xn, const YBuf<STORE> &Yn,
+__device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &lh, const XBuf<STORE> &Xc,
+                                          const YBuf<STORE> &Yc, const XBuf<STORE> &Xn, const YBuf<STORE> &Yn,
                                           const uint16_t *__restrict__ hist, const Dims &d, const Coef &cf, int CZ,
                                           int tix, int tiy, int tiz, const Span &sp = Span{}) {
     using L = XLds<TY>;
@@ -256,10 +264,9 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
         wq = rsrc2(Yn.q, 6 * d.n * SB);
     }
 
-    auto load_state = [&](Pl &P, uint32_t hw[4], int s) {
+    auto load_state = [&](Pl &P, uint32_t hw[4], int s, int m) {
         const int sc = s < d.nz ? s : d.nz - 1;
         const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
-        const int m = lmask;
         P.u = Io2<0>::ld(ru, (m & LD2_U) ? v4 : LD2_SKIP, o4 + fu);
         const int ov = (m & LD2_V) ? vS : LD2_SKIP;
         for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE>::ld(rv, ov, fv + oS + c * comp);
@@ -275,10 +282,9 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     };
     // 16-bit storage: load the plane's bits now, convert them a step later
     // (converting at the load would wait for it and stall the prefetch)
-    auto load_raw = [&](PlRaw &R, uint32_t hw[4], int s) {
+    auto load_raw = [&](PlRaw &R, uint32_t hw[4], int s, int m) {
         const int sc = s < d.nz ? s : d.nz - 1;
         const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
-        const int m = lmask;
         R.u = __builtin_amdgcn_raw_buffer_load_b32(ru, (m & LD2_U) ? v4 : LD2_SKIP, o4, 0);
         const int ov = (m & LD2_V) ? vS : LD2_SKIP;
         for (int c = 0; c < 3; c++) R.v[c] = Io2<STORE == 0 ? 1 : STORE>::raw(rv, ov, oS + c * comp);
@@ -405,7 +411,6 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     };
     PlH a0, a1, a2;
     Pl b0, b1, b2;
-    uint32_t hB[4] = {0u, 0u, 0u, 0u};
     a0.f.u = 0.0f;
     for (int c = 0; c < 3; c++) a0.f.p[c] = a0.f.v[c] = 0.0f;
     for (int c = 0; c < 6; c++) a0.f.q[c] = 0.0f;
@@ -417,8 +422,8 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
     const int sB0 = max(B.z0 - 1, 0), sB1 = B.zl + 1;
     const int s_end = sB1 + 2;
     PlRaw R;  // 16-bit storage: the plane in flight
-    if (STORE == 0) load_state(a1.f, a1.h, sA0);
-    else load_raw(R, a1.h, sA0);
+    if (STORE == 0) load_state(a1.f, a1.h, sA0, lmask);
+    else load_raw(R, a1.h, sA0, lmask);
 
     // one plane step: stage A on (prev, cur, next) = (ap, ac, an), stage B on
     // (prev, cur) = (bp, bc), stage A's result into bo
@@ -426,19 +431,29 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
         const bool runA = s <= sA1;
         const int sb = s - 2;
         const bool runB = sb >= sB0;
-        if (STORE == 0) {
-            if (runA && s + 1 <= sA1) load_state(an.f, an.h, s + 1);
-        } else {
-            if (runA) convert(R, ac.f);
-            if (runA && s + 1 <= sA1) load_raw(R, an.h, s + 1);
-        }
+        if (STORE != 0 && runA) convert(R, ac.f);
         // phase 1
         if (runA) publish(la, A, ac.f, ap.f);
         if (runB) publish(lb, B, bc, bp);
+        // prefetch plane s+1, issued at every step (with every field masked
+        // off when stage A needs no further plane): the memory counter then
+        // sees the same loads on every path and waits for exactly the plane
+        // in use, not for the prefetch in flight
+        const int pm = (runA && s + 1 <= sA1) ? lmask : 0;
+        if (STORE == 0) load_state(an.f, an.h, s + 1, pm);
+        else load_raw(R, an.h, s + 1, pm);
         lds_barrier2();
         // phase 2
-        if (runA) primal(la, A, ac.f, ap.f, ac.h, s);
-        if (runB) primal(lb, B, bc, bp, hB, sb);
+        if (runA) {
+            primal(la, A, ac.f, ap.f, ac.h, s);
+            // stage B reads this plane's histogram two steps later
+            lh.h[s % 3][threadIdx.x] = make_uint4(ac.h[0], ac.h[1], ac.h[2], ac.h[3]);
+        }
+        if (runB) {
+            const uint4 hv = lh.h[sb % 3][threadIdx.x];
+            const uint32_t hB[4] = {hv.x, hv.y, hv.z, hv.w};
+            primal(lb, B, bc, bp, hB, sb);
+        }
         lds_barrier2();
         // phase 3 (stage B first: its previous plane is dead before stage A's
         // result, which takes its slot two steps later, is formed)
@@ -456,14 +471,14 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, const XBuf
             }
         }
         if (runA) dual(la, A, ap.f, s, bo);
-        // the histogram of plane s-1 serves stage B at the next step
-        for (int c = 0; c < 4; c++) hB[c] = ap.h[c];
     };
+    // No early exit inside the unrolled loop: one or two trailing steps past
+    // s_end load and store nothing, and without the exits the values in flight
+    // need no copies at the loop's merge points (a copy of a register whose
+    // load is in flight waits for every memory operation of the wave).
     for (int s = sA0; s <= s_end; s += 3) {
         step(a0, a1, a2, b0, b1, b2, s);
-        if (s + 1 > s_end) break;
         step(a1, a2, a0, b1, b2, b0, s + 1);
-        if (s + 2 > s_end) break;
         step(a2, a0, a1, b2, b0, b1, s + 2);
     }
 }
@@ -473,12 +488,13 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     k_fused2_tiled(XBuf<STORE> Xc, YBuf<STORE> Yc, XBuf<STORE> Xn, YBuf<STORE> Yn, const uint16_t *__restrict__ hist,
                    Dims d, Coef cf, int CZ, int ntx, int nty, int ntz, Span sp) {
     __shared__ XLds<TY> la, lb;
+    __shared__ HLds<TY> lh;
     // XCD-aware tile order, as in the one-iteration kernel
     const int nb = ntx * nty * ntz;
     const int per = (nb + 7) / 8;
     const int T = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (T >= nb) return;
-    run_tile2<STORE, TY, SCP, TV, UNI>(la, lb, Xc, Yc, Xn, Yn, hist, d, cf, CZ, T % ntx, (T / ntx) % nty,
+    run_tile2<STORE, TY, SCP, TV, UNI>(la, lb, lh, Xc, Yc, Xn, Yn, hist, d, cf, CZ, T % ntx, (T / ntx) % nty,
                                        T / (ntx * nty), sp);
 }
 
@@ -491,6 +507,7 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     k_fused2_batch(const BatchBlock *__restrict__ blocks, const int4 *__restrict__ tiles, int ntiles, int *counters,
                    Coef cf, int flip) {
     __shared__ XLds<TY> la, lb;
+    __shared__ HLds<TY> lh;
     __shared__ int s_tile;
     const int seg_len = (ntiles + 7) / 8;
     const int home = (int)(blockIdx.x % 8);
@@ -510,7 +527,8 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
             XBuf<STORE> Xn{bb.u[xc ^ 1], (typename Store<STORE>::T *)bb.v[xc ^ 1]};
             YBuf<STORE> Yc{(typename Store<STORE>::T *)bb.p[yc], (typename Store<STORE>::T *)bb.q[yc]};
             YBuf<STORE> Yn{(typename Store<STORE>::T *)bb.p[yc ^ 1], (typename Store<STORE>::T *)bb.q[yc ^ 1]};
-            run_tile2<STORE, TY, 0>(la, lb, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz, tr.y & 0xffff, tr.y >> 16, tr.z);
+            run_tile2<STORE, TY, 0>(la, lb, lh, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz, tr.y & 0xffff, tr.y >> 16,
+                                    tr.z);
             lds_barrier2();  // the tile's LDS reads are done before the next tile writes
         }
     }
