@@ -477,7 +477,9 @@ def bench_city_batch(args):
     tune = tuner.tune(grids, storage)
     one = tune["by_schedule"]["fused"]
     log(f"autotune {time.perf_counter() - t0:.1f} s: {tune['schedule']} tile_y {tune['tile_y']}, classes "
-        + ", ".join(f"{k}:{v['best']}" for k, v in tune["classes"].items()))
+        + ", ".join(f"{k}:{v['best']}" for k, v in tune["classes"].items())
+        + f"; checked on the batch: {tune['checked_on_batch']}")
+    tz_solo = tune["tile_z"] if tune["tile_z"] is not None else [0] * len(grids)
     # the autotuner's pick (the headline); the library's default batched
     # schedule (two iterations per launch, 64 x 7 tiles, chunks of up to 32
     # planes); the best one-iteration-per-launch shapes; blocks one by one
@@ -503,7 +505,7 @@ def bench_city_batch(args):
 
     def plain():
         # one by one with the tuned schedule and shapes
-        for st, u0, h, tz in zip(states, u0s, hists, tune["tile_z"]):
+        for st, u0, h, tz in zip(states, u0s, hists, tz_solo):
             st.reset(u0)
             ctx.solve(st.grid, h, None, tgv.Params(iters=iters, storage=storage, tile_y=tune["tile_y"], tile_z=tz,
                                                    schedule=p_tuned.schedule), state=st)
@@ -552,7 +554,8 @@ def bench_city_batch(args):
         "config": {"workload": "city_batch", "blocks": len(grids), "edge": "log-uniform 32..128 + 2 halo",
                    "iters": iters, "cameras": len(sc.cams), "image": [W, H], "padded_voxels": padded,
                    "interior_voxels": interior, "tuned": {"schedule": tune["schedule"], "tile_y": tune["tile_y"],
-                                                          "classes": tune["classes"]}},
+                                                          "classes": tune["classes"],
+                                                          "checked_on_batch": tune["checked_on_batch"]}},
         "batched": {"s": tb, "blocks_per_s": len(grids) / tb, "updates_per_s_interior": interior * iters / tb,
                     "algorithmic_GBs": bpv * padded * iters / tb / 1e9,
                     "shapes": "autotuned (schedule, tile_y, per-block tile_z)"},

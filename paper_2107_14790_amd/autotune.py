@@ -13,8 +13,13 @@ The autotuner groups blocks into padded-edge classes, times every candidate
 the batched C-ABI call (synthetic histograms, a few iterations), then picks
 the (schedule, tile_y) whose time summed over the classes (each scaled from
 its sample to the class's voxels) is least, and for each class the tile_z
-that is fastest at that pair.  Results are cached per device, storage and
-class.  The measurement is a function argument, so the search itself runs
+that is fastest at that pair.  A class timed alone is not the batch: in the
+mix the work queue has tiles to spare, and short chunks that fill the chip
+for one class only add halo planes there.  So the class-wise choice is
+checked on a sample of the batch itself against a few alternatives (the
+same pair with deeper or uniform chunks, the library's default) and the
+fastest of them is taken.  Results are cached per device, storage and
+class.  The measurements are function arguments, so the search itself runs
 without a GPU (tests give it a model).
 """
 from __future__ import annotations
@@ -31,6 +36,7 @@ TILE_Y = {"fused": (4, 8, 12), "fused2": (4, 6, 7)}
 TILE_Z = (8, 16, 32, 64, 128)
 CLASS_EDGES = (48, 80, 128, 192, 1 << 30)  # padded edge upper bounds of the classes
 TUNE_ITERS = 9  # one dual step, four two-iteration launches (or eight one-iteration ones), one primal step
+MIX_BLOCKS = 96  # blocks of the batch sample the class-wise choice is checked on
 
 
 def edge_class(n: Sequence[int]) -> int:
@@ -82,10 +88,13 @@ def pick(per_class: Dict[int, dict], weight: Dict[int, float], schedules=SCHED_N
 
 class Autotuner:
     def __init__(self, ctx=None, cache_path: str = None, iters: int = TUNE_ITERS, reps: int = 3,
-                 measure: Callable = None, device_name: str = None):
+                 measure: Callable = None, device_name: str = None, measure_mix: Callable = None):
         """ctx: a libtgv Context (None when a `measure` model is given).
         measure(shapes, storage, schedule, tile_y, tile_z) -> ms replaces the
-        GPU timing (for tests)."""
+        GPU timing of a class sample, measure_mix(shapes, storage, schedule,
+        tile_y, tile_z_list or None) -> ms that of a batch sample (for tests;
+        with a `measure` model and no `measure_mix` the check on the batch
+        is skipped)."""
         self.ctx = ctx
         self.iters = iters
         self.reps = reps
@@ -95,6 +104,7 @@ class Autotuner:
             with open(cache_path) as f:
                 self.cache = json.load(f)
         self.measure = measure or self._gpu_measure
+        self.measure_mix = measure_mix or (None if measure else self._gpu_measure_mix)
         if device_name is None:
             import torch
             device_name = torch.cuda.get_device_name(ctx.device)
@@ -132,6 +142,29 @@ class Autotuner:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
             self.ctx.solve_batch(states, hists, p, tile_z=[tz] * len(states))
+            e1.record(s)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    def _gpu_measure_mix(self, shapes, storage, sched, ty, tz_list) -> float:
+        """Time one batched solve of these shapes with per-block chunks
+        (None: the library's default)."""
+        import torch
+        import paper_2107_14790_amd as tgv
+        key = (tuple(tuple(s) for s in shapes), storage)
+        if self._batch is None or self._batch[0] != key:
+            self.measure(shapes, storage, sched, ty, 32)  # builds the sample's states
+        _, states, hists = self._batch
+        p = tgv.Params(iters=self.iters, storage=storage, tile_y=ty,
+                       schedule=tgv.SCHED_FUSED2 if sched == "fused2" else tgv.SCHED_FUSED)
+        s = torch.cuda.current_stream()
+        self.ctx.solve_batch(states, hists, p, tile_z=tz_list)  # warm
+        best = float("inf")
+        for _ in range(self.reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            self.ctx.solve_batch(states, hists, p, tile_z=tz_list)
             e1.record(s)
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1))
@@ -179,12 +212,40 @@ class Autotuner:
                   for cls, shapes in classes.items()}
         choice = pick(per_class, weight)
         tile_z = [choice["tile_z_of_class"][edge_class(g.n)] for g in grids]
+        best_sched, best_ty = choice["schedule"], choice["tile_y"]
+        checked = None
+        if self.measure_mix is not None:
+            # the class-wise choice against alternatives, on a sample of the batch
+            rng = np.random.default_rng(1)
+            idx = sorted(rng.choice(len(grids), size=min(len(grids), MIX_BLOCKS), replace=False).tolist())
+            shapes = [tuple(int(v) for v in grids[i].n) for i in idx]
+            tz_class = choice["tile_z_of_class"]
+            alts = {
+                "class-wise": (best_sched, best_ty, [tz_class[edge_class(n)] for n in shapes]),
+                "class-wise, chunks doubled": (best_sched, best_ty, [min(2 * tz_class[edge_class(n)], TILE_Z[-1])
+                                                                     for n in shapes]),
+                "uniform chunks of 32": (best_sched, best_ty, [32] * len(shapes)),
+                "library default": ("fused2", 7, None),
+            }
+            checked = {name: float(self.measure_mix(shapes, storage, a, b, c)) for name, (a, b, c) in alts.items()}
+            self._release()
+            win = min(checked, key=checked.get)
+            best_sched, best_ty, _ = alts[win]
+            if win == "class-wise":
+                pass
+            elif win == "class-wise, chunks doubled":
+                tile_z = [min(2 * tz_class[edge_class(g.n)], TILE_Z[-1]) for g in grids]
+            elif win == "uniform chunks of 32":
+                tile_z = [32] * len(grids)
+            else:
+                tile_z = None
+            checked = {"sample_blocks": len(shapes), "ms": checked, "chosen": win}
         by_schedule = {}
         for sched in SCHED_NAMES:
             c = pick(per_class, weight, (sched,))
             by_schedule[sched] = {"tile_y": c["tile_y"], "predicted_ms": c["predicted_ms"],
                                   "tile_z": [c["tile_z_of_class"][edge_class(g.n)] for g in grids]}
-        return {"schedule": choice["schedule"], "tile_y": choice["tile_y"], "tile_z": tile_z,
+        return {"schedule": best_sched, "tile_y": best_ty, "tile_z": tile_z, "checked_on_batch": checked,
                 "predicted_ms": choice["predicted_ms"], "by_schedule": by_schedule,
                 "classes": {str(k): {"best": v["best"], "ms": v["ms"], "tile_z": choice["tile_z_of_class"][k]}
                             for k, v in per_class.items()}}

@@ -86,3 +86,35 @@ def test_pick_ignores_pairs_missing_on_a_class():
                  1: {"all": {"fused,4,8": 2.0}}}
     r = autotune.pick(per_class, {0: 1.0, 1: 1.0})
     assert r["schedule"] == "fused" and r["tile_y"] == 4
+
+
+def test_class_wise_choice_is_checked_on_the_batch():
+    """Timed alone, small blocks want short chunks (they fill the chip); in
+    the mixed batch short chunks only add halo planes.  The check on a
+    sample of the batch takes the faster alternative, and the library
+    default when it beats every tuned variant."""
+    grids = [G((36, 36, 36))] * 40 + [G((120, 120, 120))] * 6
+    measure, _ = model(("fused2", 7, 8), ("fused2", 7, 32))
+    mixes = []
+
+    def mix_deep(shapes, storage, sched, ty, tz):
+        mixes.append((len(shapes), sched, ty, None if tz is None else tuple(tz)))
+        vox = sum(a * b * c for a, b, c in shapes)
+        if tz is None:
+            return vox * 1e-6 * 1.15
+        halo = sum(a * b * c * 4.0 / t for (a, b, c), t in zip(shapes, tz))
+        return (vox + halo) * 1e-6
+
+    r = autotune.Autotuner(measure=measure, measure_mix=mix_deep, device_name="model").tune(grids)
+    assert r["schedule"] == "fused2" and r["tile_y"] == 7
+    assert r["checked_on_batch"]["chosen"] == "class-wise, chunks doubled"
+    assert r["tile_z"][0] == 16 and r["tile_z"][-1] == 64
+    assert all(n == len(grids) for n, _, _, _ in mixes) and len(mixes) == 4
+
+    def mix_default(shapes, storage, sched, ty, tz):
+        vox = sum(a * b * c for a, b, c in shapes)
+        return vox * 1e-6 * (0.9 if tz is None else 1.0)
+
+    r2 = autotune.Autotuner(measure=measure, measure_mix=mix_default, device_name="model").tune(grids)
+    assert r2["checked_on_batch"]["chosen"] == "library default"
+    assert r2["schedule"] == "fused2" and r2["tile_y"] == 7 and r2["tile_z"] is None

@@ -216,8 +216,9 @@ def test_autotuned_batch_equals_solo(ctx):
             self.n = n
 
     tuned = Autotuner(ctx, iters=5, reps=1).tune([Gn(shape) for shape, _, _, _ in blocks])
-    say("tuned", tuned["schedule"], tuned["tile_y"], tuned["tile_z"])
-    assert len(tuned["tile_z"]) == len(blocks)
+    say("tuned", tuned["schedule"], tuned["tile_y"], tuned["tile_z"], tuned["checked_on_batch"])
+    assert tuned["tile_z"] is None or len(tuned["tile_z"]) == len(blocks)
+    assert tuned["checked_on_batch"]["chosen"] in tuned["checked_on_batch"]["ms"]
     iters = 12
     solo, states, hists = [], [], []
     for (shape, halo, hist, u0), g in zip(blocks, grids):
