@@ -29,6 +29,10 @@ namespace tgv {
 namespace {
 
 constexpr int TX = 64;
+// a lane offset past the end of every buffer: a raw buffer load there reads
+// 0 and a store there is dropped, with no memory request (blocks of the
+// tiled kernels stay below 2^31 bytes per buffer)
+constexpr int LD_SKIP = (int)0x80000000u;
 constexpr unsigned RSRC_WORD3 = 0x00020000u;  // raw buffer, 32-bit data format
 
 // wait for this wave's LDS operations, then meet the workgroup; the memory
@@ -111,12 +115,13 @@ struct Tile {
 
     // Load plane s of the lane's column (every field, for every lane: the
     // loads stay branch-free so the compiler can issue them back to back).
-    // Load plane s of the lane's column (every field, for every lane: the
-    // loads stay branch-free so the compiler can issue them back to back).
-    __device__ __forceinline__ void load(Plane &L, int s) const {
+    // With `on` false every offset is past the end of its buffer: the loads
+    // are issued but read nothing (the raw buffer range check returns 0).
+    __device__ __forceinline__ void load(Plane &L, int s, bool on = true) const {
         // planes past the block are clamped to the last one: their values are never used
         const int sc = s < d->nz ? s : d->nz - 1;
         const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
+        const int v4 = on ? this->v4 : LD_SKIP, vS = on ? this->vS : LD_SKIP, vH = on ? this->vH : LD_SKIP;
         L.u = Io<0>::ld(ru, v4, o4);
         auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, vH, oH, 0);
         L.h[0] = hv[0];
@@ -135,7 +140,6 @@ struct Tile {
     // Carried values: UP1/UB1 = u+ and ubar of plane s-1, VB2 = vbar of plane s-2.
     __device__ __forceinline__ void step(const Plane &prev, const Plane &cur, Plane &nxt, int s, int s1, float &UP1,
                                          float &UB1, float VB2[3]) const {
-        if (s + 1 <= s1) load(nxt, s + 1);
         const bool have_s = s < d->nz;
         const bool do_u = s >= z0 && have_s;
         const int sv = s - 1;
@@ -152,6 +156,11 @@ struct Tile {
             sQ[3 * NE + e] = prev.q[4];
             sQ[4 * NE + e] = prev.q[5];
         }
+        // prefetch plane s+1, issued at every step (reading nothing past the
+        // chunk) and after the plane in use is published: the memory counter
+        // sees the same operations on every path, so a wait for the plane in
+        // use never waits for the prefetch in flight
+        load(nxt, s + 1, s + 1 <= s1);
         lds_barrier();
 
         // ---- 2. primal updates: u+ at plane s, v+ at plane s-1
@@ -196,7 +205,10 @@ struct Tile {
         lds_barrier();
 
         // ---- 3. dual update of plane s-1 and stores
-        if (core && do_dual) {
+        float p[3] = {0.0f, 0.0f, 0.0f};
+        float q[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        const bool made = core && do_dual;
+        if (made) {
             const bool mlo[3] = {mlo_x, mlo_y, zlo_v}, mhi[3] = {mhi_x, mhi_y, zhi_v};
             float ub_hi[3], vb_lo[3][3];
             const float ux = sU[e + 1], uy = sU[e + EX];
@@ -210,19 +222,25 @@ struct Tile {
                 vb_lo[1][i] = mlo_y ? by : 0.0f;
                 vb_lo[2][i] = zlo_v ? VB2[i] : 0.0f;
             }
-            float p[3] = {prev.p[0], prev.p[1], prev.p[2]};
-            float q[6] = {prev.q[0], prev.q[1], prev.q[2], prev.q[3], prev.q[4], prev.q[5]};
+#pragma unroll
+            for (int c = 0; c < 3; c++) p[c] = prev.p[c];
+#pragma unroll
+            for (int c = 0; c < 6; c++) q[c] = prev.q[c];
             dual_pq(p, q, UB1, ub_hi, VB, vb_lo, mlo, mhi, *cf);
-            if (in) {
-                const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
-                Io<0>::st<SCP>(wu, v4, o4, UP1);
+        }
+        {
+            // the stores are issued at every step; lanes without a result get
+            // an offset past the end of the buffer, which drops the store
+            const int svc = sv > 0 ? sv : 0;
+            const int o4 = (int)(plane4 * svc), oS = (int)(planeS * svc);
+            const int a4 = (made && in) ? v4 : LD_SKIP, aS = (made && in) ? vS : LD_SKIP;
+            Io<0>::st<SCP>(wu, a4, o4, UP1);
 #pragma unroll
-                for (int c = 0; c < 3; c++) Io<STORE>::template st<SCP>(wv, vS, oS + c * comp, VP[c]);
+            for (int c = 0; c < 3; c++) Io<STORE>::template st<SCP>(wv, aS, oS + c * comp, VP[c]);
 #pragma unroll
-                for (int c = 0; c < 3; c++) Io<STORE>::template st<SCP>(wp, vS, oS + c * comp, p[c]);
+            for (int c = 0; c < 3; c++) Io<STORE>::template st<SCP>(wp, aS, oS + c * comp, p[c]);
 #pragma unroll
-                for (int c = 0; c < 6; c++) Io<STORE>::template st<SCP>(wq, vS, oS + c * comp, q[c]);
-            }
+            for (int c = 0; c < 6; c++) Io<STORE>::template st<SCP>(wq, aS, oS + c * comp, q[c]);
         }
         UP1 = UP;
         UB1 = UB;
@@ -329,11 +347,11 @@ __device__ __forceinline__ void run_tile(TileLds<TY> &lds, const XBuf<STORE> &Xc
 #pragma unroll
     for (int c = 0; c < 6; c++) A.q[c] = 0.0f;
     t.load(B, s0);
+    // no early exit inside the unrolled loop: one or two trailing steps
+    // past s1 load and store nothing, and the loop keeps one shape
     for (int s = s0; s <= s1; s += 3) {
         t.step(A, B, C, s, s1, UP1, UB1, VB2);
-        if (s + 1 > s1) break;
         t.step(B, C, A, s + 1, s1, UP1, UB1, VB2);
-        if (s + 2 > s1) break;
         t.step(C, A, B, s + 2, s1, UP1, UB1, VB2);
     }
 }
