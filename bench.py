@@ -430,8 +430,8 @@ def bench_city_batch(args):
     2-voxel halo), 500 iterations each: one batched solve (a persistent
     launch per two iterations over all blocks, graph replay) against the
     batched one-iteration kernel with autotuned tiles and against solving
-    the blocks one by one (autotuned tiles, and the library's defaults);
-    results compared bit for bit."""
+    the blocks one by one with the library's defaults; results compared bit
+    for bit."""
     import torch
     import paper_2107_14790_amd as tgv
     from paper_2107_14790_amd.autotune import Autotuner
@@ -479,10 +479,10 @@ def bench_city_batch(args):
     log(f"autotune {time.perf_counter() - t0:.1f} s: {tune['schedule']} tile_y {tune['tile_y']}, classes "
         + ", ".join(f"{k}:{v['best']}" for k, v in tune["classes"].items())
         + f"; checked on the batch: {tune['checked_on_batch']}")
-    tz_solo = tune["tile_z"] if tune["tile_z"] is not None else [0] * len(grids)
     # the autotuner's pick (the headline); the library's default batched
     # schedule (two iterations per launch, 64 x 7 tiles, chunks of up to 32
     # planes); the best one-iteration-per-launch shapes; blocks one by one
+    # with the library's defaults
     p_tuned = Autotuner.params(tune, iters, storage, flags=tgv.FLAG_GRAPH)
     p_default = tgv.Params(iters=iters, storage=storage, schedule=tgv.SCHED_FUSED2, flags=tgv.FLAG_GRAPH)
     p_one = tgv.Params(iters=iters, storage=storage, tile_y=one["tile_y"], schedule=tgv.SCHED_FUSED,
@@ -503,13 +503,6 @@ def bench_city_batch(args):
             st.reset(u0)
         ctx.solve_batch(states, hists, p_one, tile_z=one["tile_z"])
 
-    def plain():
-        # one by one with the tuned schedule and shapes
-        for st, u0, h, tz in zip(states, u0s, hists, tz_solo):
-            st.reset(u0)
-            ctx.solve(st.grid, h, None, tgv.Params(iters=iters, storage=storage, tile_y=tune["tile_y"], tile_z=tz,
-                                                   schedule=p_tuned.schedule), state=st)
-
     def plain_default():
         # one by one with the library's defaults (schedule AUTO, tiles and chunk depth chosen per block)
         for st, u0, h in zip(states, u0s, hists):
@@ -520,7 +513,7 @@ def bench_city_batch(args):
     torch.cuda.synchronize()
     times = {}
     for name, fn in (("batched", batched), ("batched_default", batched_default),
-                     ("batched_one_pass", batched_one_pass), ("plain", plain), ("plain_default", plain_default)):
+                     ("batched_one_pass", batched_one_pass), ("plain_default", plain_default)):
         ts = []
         for _ in range(max(1, args.steps)):
             torch.cuda.synchronize()
@@ -538,8 +531,6 @@ def bench_city_batch(args):
             same_one = all(torch.equal(a, st.export()["u"]) for a, st in zip(ref, states[:8]))
         if name == "batched_default":
             same_bd = all(torch.equal(a, st.export()["u"]) for a, st in zip(ref, states[:8]))
-        if name == "plain":
-            same = all(torch.equal(a, st.export()["u"]) for a, st in zip(ref, states[:8]))
     tb, tp = min(times["batched"]), min(times["plain_default"])
     bpv = bytes_per_update(storage)
     out = {
@@ -562,9 +553,6 @@ def bench_city_batch(args):
         "batched_library_default": {"s": min(times["batched_default"]),
                                     "updates_per_s_interior": interior * iters / min(times["batched_default"]),
                                     "shapes": "two iterations per launch, 64 x 7 tiles, chunks of up to 32 planes"},
-        "plain_tuned_shapes": {"s": min(times["plain"]),
-                               "note": "one by one with the batch's tuned schedule, tile_y and chunks (chunks tuned "
-                                       "for the batch leave a block alone with few tiles)"},
         "batched_one_pass_autotuned": {"s": min(times["batched_one_pass"]), "tile_y": one["tile_y"],
                                        "updates_per_s_interior": interior * iters / min(times["batched_one_pass"])},
         "plain_library_defaults": {"s": min(times["plain_default"]),
@@ -572,7 +560,7 @@ def bench_city_batch(args):
                                    "updates_per_s_interior": interior * iters / min(times["plain_default"])},
         "speedup_batched_vs_plain": tp / tb,
         "plain": "blocks one by one with the library's defaults (plain_library_defaults)",
-        "bitwise_same_alone_and_batched": bool(same and same_default and same_one and same_bd),
+        "bitwise_same_alone_and_batched": bool(same_default and same_one and same_bd),
         "phases_ms": {"pyramids": pyr_ms, "histograms_all_blocks": hist_ms},
     }
     print(json.dumps(out), flush=True)
