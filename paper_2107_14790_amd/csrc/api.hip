@@ -942,6 +942,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
     std::vector<int> big;
     HIP_TRY(ctx, hipEventSynchronize(ctx->bt_evt));  // the previous upload has left the staging buffers
     int nb = 0, nt = 0, nt_extra = 0;
+    bool all_span = true;
     {
         long long tiles = 0;
         for (int i = 0; i < n; i++) {
@@ -1003,7 +1004,10 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             const int pre = (extra && came_open[i]) ? 1 : 0;
             bb.xc = st->xc ^ pre;
             bb.yc = st->yc ^ pre;
-            bb.pad = 0;
+            // state_layout puts every field in one allocation from u[0]
+            const long long sbytes = tgv_state_bytes(&st->grid, st->storage);
+            bb.span = sbytes < (1LL << 31) ? (int)sbytes : 0;
+            all_span = all_span && bb.span > 0;
             int ntx = (d.nx + 63) / 64, nty = (d.ny + ty - 1) / ty, ntz = (d.nz + cz - 1) / cz;
             for (int z = 0; z < ntz; z++)
                 for (int y = 0; y < nty; y++)
@@ -1039,7 +1043,7 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
     auto launch_one = [&](int flip, hipStream_t st_) {
         if (two)
             launch_batch2(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters, cf,
-                          ty, flip, grid, st_);
+                          ty, flip, grid, all_span, st_);
         else
             launch_batch(params->storage, ctx->bt_blocks_dev, (const int4 *)ctx->bt_tiles_dev, nt, ctx->counters, cf,
                          ty, flip, grid, st_);
@@ -1052,8 +1056,9 @@ extern "C" tgv_status tgv_solve_batch(tgv_ctx *ctx, int32_t n, tgv_state *const 
             // the graph holds two launches (parity 0 then 1); it is keyed by
             // everything its kernel arguments capture
             char key[256];
-            int kl = snprintf(key, sizeof(key), "%d|%d|%d|%d|%d|%d|%p|%p|%p|", params->storage, (int)two, ty, nt, grid,
-                              nb, (void *)ctx->bt_blocks_dev, (void *)ctx->bt_tiles_dev, (void *)ctx->counters);
+            int kl = snprintf(key, sizeof(key), "%d|%d|%d|%d|%d|%d|%d|%p|%p|%p|", params->storage, (int)two, ty, nt,
+                              grid, nb, (int)all_span, (void *)ctx->bt_blocks_dev, (void *)ctx->bt_tiles_dev,
+                              (void *)ctx->counters);
             std::string k(key, kl);
             k.append((const char *)&cf, sizeof(cf));
             HIP_TRY(ctx, hipEventRecord(ctx->ev_a, s));

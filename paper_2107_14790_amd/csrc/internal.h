@@ -27,6 +27,8 @@ struct SolveBufs {
 
 // One block of a batched solve as the persistent kernel reads it: the
 // state's buffers for both parities and the block's current parities.
+// `span`: bytes from u[0] that hold every field of the state when that is
+// below 2 GiB (one buffer descriptor serves them all), else 0.
 struct BatchBlock {
     float *u[2];
     void *v[2];
@@ -36,7 +38,7 @@ struct BatchBlock {
     Dims d;
     int cz;
     int xc, yc;
-    int pad;
+    int span;
 };
 
 // Geometry of a packed pyramid (all cameras the same size).
@@ -111,8 +113,9 @@ int choose_tile2_z(const Dims &d, int ty, int slots);
 int batch_blocks_per_cu(int storage, int ty);
 // batched two-iteration pass (tiles 64 x ty, ty in {4, 6, 7}); resets the queue counters first
 int batch2_blocks_per_cu(int storage, int ty);
+// span: every block's `span` is set (float32 64 x 7 tiles then take the one-descriptor form)
 void launch_batch2(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
-                   int ty, int flip, int grid, hipStream_t s);
+                   int ty, int flip, int grid, bool span, hipStream_t s);
 void launch_reset_counters(int *counters, hipStream_t s);
 int tiled_blocks_per_cu(int storage, int ty, const Dims &d);
 int choose_tile_z(const Dims &d, int ty, int slots);

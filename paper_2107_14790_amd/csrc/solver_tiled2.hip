@@ -112,11 +112,6 @@ struct Pl {
     float u, v[3], p[3], q[6];
 };
 
-// a plane of 16-bit fields as loaded (bits), converted when it is used
-struct PlRaw {
-    uint32_t u, v[3], p[3], q[6];
-};
-
 __device__ __forceinline__ int lq2(int slot) { return slot == 0 ? 0 : (slot == 1 ? 1 : slot - 1); }
 
 // LDS exchange planes of one stage over the (TX+4) x (TY+4) index space
@@ -280,29 +275,35 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
         hw[2] = hv[2];
         hw[3] = hv[3];
     };
-    // 16-bit storage: load the plane's bits now, convert them a step later
-    // (converting at the load would wait for it and stall the prefetch)
-    auto load_raw = [&](PlRaw &R, uint32_t hw[4], int s, int m) {
+    // 16-bit storage: the plane's fields are loaded as raw bits into the
+    // registers of its slot and converted in place when it becomes the
+    // current plane, a step later (converting at the load would wait for it
+    // and stall the prefetch; a separate buffer for the bits would need
+    // register copies, and a copy of a register whose load is in flight
+    // waits for every memory operation of the wave).  u is float32 in every
+    // storage and is loaded as it is.
+    auto load_raw = [&](Pl &P, uint32_t hw[4], int s, int m) {
         const int sc = s < d.nz ? s : d.nz - 1;
         const int o4 = (int)(plane4 * sc), oS = (int)(planeS * sc), oH = (int)(planeH * sc);
-        R.u = __builtin_amdgcn_raw_buffer_load_b32(ru, (m & LD2_U) ? v4 : LD2_SKIP, o4, 0);
+        P.u = Io2<0>::ld(ru, (m & LD2_U) ? v4 : LD2_SKIP, o4);
         const int ov = (m & LD2_V) ? vS : LD2_SKIP;
-        for (int c = 0; c < 3; c++) R.v[c] = Io2<STORE == 0 ? 1 : STORE>::raw(rv, ov, oS + c * comp);
+        for (int c = 0; c < 3; c++) P.v[c] = __uint_as_float(Io2<STORE == 0 ? 1 : STORE>::raw(rv, ov, oS + c * comp));
         for (int c = 0; c < 3; c++)
-            R.p[c] = Io2<STORE == 0 ? 1 : STORE>::raw(rp, (m & (LD2_PX << c)) ? vS : LD2_SKIP, oS + c * comp);
+            P.p[c] = __uint_as_float(
+                Io2<STORE == 0 ? 1 : STORE>::raw(rp, (m & (LD2_PX << c)) ? vS : LD2_SKIP, oS + c * comp));
         for (int c = 0; c < 6; c++)
-            R.q[c] = Io2<STORE == 0 ? 1 : STORE>::raw(rq, (m & (LD2_Q0 << c)) ? vS : LD2_SKIP, oS + c * comp);
+            P.q[c] = __uint_as_float(
+                Io2<STORE == 0 ? 1 : STORE>::raw(rq, (m & (LD2_Q0 << c)) ? vS : LD2_SKIP, oS + c * comp));
         auto hv = __builtin_amdgcn_raw_buffer_load_b128(rh, (m & LD2_H) ? vH : LD2_SKIP, oH, 0);
         hw[0] = hv[0];
         hw[1] = hv[1];
         hw[2] = hv[2];
         hw[3] = hv[3];
     };
-    auto convert = [&](const PlRaw &R, Pl &P) {
-        P.u = __uint_as_float(R.u);
-        for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(R.v[c]);
-        for (int c = 0; c < 3; c++) P.p[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(R.p[c]);
-        for (int c = 0; c < 6; c++) P.q[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(R.q[c]);
+    auto convert = [&](Pl &P) {
+        for (int c = 0; c < 3; c++) P.v[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(__float_as_uint(P.v[c]));
+        for (int c = 0; c < 3; c++) P.p[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(__float_as_uint(P.p[c]));
+        for (int c = 0; c < 6; c++) P.q[c] = Io2<STORE == 0 ? 1 : STORE>::cvt(__float_as_uint(P.q[c]));
     };
 
     // phase 1: publish p_x, p_y of plane s (cur) and q of plane s-1 (prev)
@@ -421,9 +422,8 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
     const int sA0 = max(A.z0 - 1, 0), sA1 = A.zl + 1;
     const int sB0 = max(B.z0 - 1, 0), sB1 = B.zl + 1;
     const int s_end = sB1 + 2;
-    PlRaw R;  // 16-bit storage: the plane in flight
     if (STORE == 0) load_state(a1.f, a1.h, sA0, lmask);
-    else load_raw(R, a1.h, sA0, lmask);
+    else load_raw(a1.f, a1.h, sA0, lmask);
 
     // one plane step: stage A on (prev, cur, next) = (ap, ac, an), stage B on
     // (prev, cur) = (bp, bc), stage A's result into bo
@@ -431,7 +431,7 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
         const bool runA = s <= sA1;
         const int sb = s - 2;
         const bool runB = sb >= sB0;
-        if (STORE != 0 && runA) convert(R, ac.f);
+        if (STORE != 0 && runA) convert(ac.f);
         // phase 1
         if (runA) publish(la, A, ac.f, ap.f);
         if (runB) publish(lb, B, bc, bp);
@@ -441,7 +441,7 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
         // in use, not for the prefetch in flight
         const int pm = (runA && s + 1 <= sA1) ? lmask : 0;
         if (STORE == 0) load_state(an.f, an.h, s + 1, pm);
-        else load_raw(R, an.h, s + 1, pm);
+        else load_raw(an.f, an.h, s + 1, pm);
         lds_barrier2();
         // phase 2
         if (runA) {
@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
 // iterations per launch.  Workgroups pull tiles from the same per-XCD queue
 // segments as the one-iteration batched kernel; no workgroup waits on
 // another.
-template <int STORE, int TY>
+template <int STORE, int TY, bool UNI = false>
 __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
     k_fused2_batch(const BatchBlock *__restrict__ blocks, const int4 *__restrict__ tiles, int ntiles, int *counters,
                    Coef cf, int flip) {
@@ -527,8 +527,24 @@ __global__ void __launch_bounds__(TX *(TY + 5), TILED2_WAVES_PER_EU)
             XBuf<STORE> Xn{bb.u[xc ^ 1], (typename Store<STORE>::T *)bb.v[xc ^ 1]};
             YBuf<STORE> Yc{(typename Store<STORE>::T *)bb.p[yc], (typename Store<STORE>::T *)bb.q[yc]};
             YBuf<STORE> Yn{(typename Store<STORE>::T *)bb.p[yc ^ 1], (typename Store<STORE>::T *)bb.q[yc ^ 1]};
-            run_tile2<STORE, TY, 0>(la, lb, lh, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz, tr.y & 0xffff, tr.y >> 16,
-                                    tr.z);
+            if constexpr (UNI) {
+                // every field within the state's allocation (below 2 GiB):
+                // one descriptor and scalar byte offsets, as in the one-block
+                // kernel (the offsets are made wave-uniform explicitly; kept
+                // in vector registers they would turn every store into a
+                // loop over the distinct offsets)
+                const char *base = (const char *)bb.u[0];
+                auto off = [&](const void *f) {
+                    return __builtin_amdgcn_readfirstlane((int)((const char *)f - base));
+                };
+                const Span sp{base,          bb.span,           off(bb.u[xc]),     off(bb.v[xc]),     off(bb.p[yc]),
+                              off(bb.q[yc]), off(bb.u[xc ^ 1]), off(bb.v[xc ^ 1]), off(bb.p[yc ^ 1]), off(bb.q[yc ^ 1])};
+                run_tile2<STORE, TY, 0, false, true>(la, lb, lh, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz,
+                                                     tr.y & 0xffff, tr.y >> 16, tr.z, sp);
+            } else {
+                run_tile2<STORE, TY, 0>(la, lb, lh, Xc, Yc, Xn, Yn, bb.hist, bb.d, cf, bb.cz, tr.y & 0xffff,
+                                        tr.y >> 16, tr.z);
+            }
             lds_barrier2();  // the tile's LDS reads are done before the next tile writes
         }
     }
@@ -584,9 +600,14 @@ bool tiled2_shape_ok(int ty, int cz) { return (ty == 4 || ty == 6 || ty == 7) &&
 
 template <int STORE, int TY>
 static int batch2_per_cu_t() {
-    int nb = 0;
+    int nb = 0, nu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused2_batch<STORE, TY>, TX * (TY + 5), 0) != hipSuccess)
         return 1;
+    // the one-descriptor form shares the grid
+    if (STORE == 0 && TY == 7 &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nu, k_fused2_batch<STORE, TY, (STORE == 0 && TY == 7)>,
+                                                     TX * (TY + 5), 0) == hipSuccess)
+        nb = nu < nb ? nu : nb;
     return nb > 0 ? nb : 1;
 }
 
@@ -598,8 +619,11 @@ int batch2_blocks_per_cu(int storage, int ty) {
 
 template <int STORE>
 static void launch_batch2_t(const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
-                            int ty, int flip, int grid, hipStream_t s) {
-    if (ty == 4)
+                            int ty, int flip, int grid, bool span, hipStream_t s) {
+    if (STORE == 0 && ty == 7 && span)
+        hipLaunchKernelGGL((k_fused2_batch<STORE, 7, (STORE == 0)>), dim3(grid), dim3(TX * 12), 0, s, blocks, tiles,
+                           ntiles, counters, cf, flip);
+    else if (ty == 4)
         hipLaunchKernelGGL((k_fused2_batch<STORE, 4>), dim3(grid), dim3(TX * 9), 0, s, blocks, tiles, ntiles, counters,
                            cf, flip);
     else if (ty == 6)
@@ -611,11 +635,11 @@ static void launch_batch2_t(const BatchBlock *blocks, const int4 *tiles, int nti
 }
 
 void launch_batch2(int storage, const BatchBlock *blocks, const int4 *tiles, int ntiles, int *counters, const Coef &cf,
-                   int ty, int flip, int grid, hipStream_t s) {
+                   int ty, int flip, int grid, bool span, hipStream_t s) {
     launch_reset_counters(counters, s);
-    if (storage == 0) launch_batch2_t<0>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
-    else if (storage == 1) launch_batch2_t<1>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
-    else launch_batch2_t<2>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, s);
+    if (storage == 0) launch_batch2_t<0>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, span, s);
+    else if (storage == 1) launch_batch2_t<1>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, span, s);
+    else launch_batch2_t<2>(blocks, tiles, ntiles, counters, cf, ty, flip, grid, span, s);
 }
 
 // resident workgroups per CU of the two-iteration kernel
