@@ -476,10 +476,24 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
     // s_end load and store nothing, and without the exits the values in flight
     // need no copies at the loop's merge points (a copy of a register whose
     // load is in flight waits for every memory operation of the wave).
-    for (int s = sA0; s <= s_end; s += 3) {
-        step(a0, a1, a2, b0, b1, b2, s);
-        step(a1, a2, a0, b1, b2, b0, s + 1);
-        step(a2, a0, a1, b2, b0, b1, s + 2);
+    if constexpr (STORE == 0) {
+        for (int s = sA0; s <= s_end; s += 3) {
+            step(a0, a1, a2, b0, b1, b2, s);
+            step(a1, a2, a0, b1, b2, b0, s + 1);
+            step(a2, a0, a1, b2, b0, b1, s + 2);
+        }
+    } else {
+        // 16-bit storage: the loop runs at least once (s_end > sA0); without
+        // the check for no pass the compiler leaves no full memory wait at
+        // its head (FP16 568 -> 552 us per launch on 256^3, BF16 565 -> 561;
+        // in float32 the same form was 1 % slower)
+        int s = sA0;
+        do {
+            step(a0, a1, a2, b0, b1, b2, s);
+            step(a1, a2, a0, b1, b2, b0, s + 1);
+            step(a2, a0, a1, b2, b0, b1, s + 2);
+            s += 3;
+        } while (s <= s_end);
     }
 }
 

@@ -53,16 +53,14 @@ def asm1(tmp_path_factory):
     return assembly("solver_tiled.hip", tmp_path_factory.mktemp("isa1"))
 
 
-# the float32 kernels the benchmark, batching and serving workloads run: the
-# two-iteration kernel with one buffer descriptor (64 x 7 tiles, streamed
-# stores) and its batched forms (one descriptor per block, and one per
-# field), the BF16 two-iteration kernel, and the one-iteration kernels
-# (64 x 8 tiles; 64 x 4 with FP16 storage).  The FP16 two-iteration kernel
-# keeps full waits where it converts the plane loaded a step earlier (the
-# compiler re-reads the loaded bits there), after the loads it needs have
-# been waited for, before the next prefetch is issued.
-TWO = ["_ZN3tgv14k_fused2_tiledILi0ELi7ELi2ELb0ELb1E", "_ZN3tgv14k_fused2_tiledILi2ELi7ELi2ELb0ELb0E",
-       "_ZN3tgv14k_fused2_batchILi0ELi7ELb0E", "_ZN3tgv14k_fused2_batchILi0ELi7ELb1E"]
+# the kernels the benchmark, batching, serving and precision workloads run:
+# the two-iteration kernel in float32 with one buffer descriptor (64 x 7
+# tiles, streamed stores), with FP16 and with BF16 storage, its float32
+# batched forms (one descriptor per block, and one per field), and the
+# one-iteration kernels (64 x 8 tiles; 64 x 4 with FP16 storage)
+TWO = ["_ZN3tgv14k_fused2_tiledILi0ELi7ELi2ELb0ELb1E", "_ZN3tgv14k_fused2_tiledILi1ELi7ELi2ELb0ELb0E",
+       "_ZN3tgv14k_fused2_tiledILi2ELi7ELi2ELb0ELb0E", "_ZN3tgv14k_fused2_batchILi0ELi7ELb0E",
+       "_ZN3tgv14k_fused2_batchILi0ELi7ELb1E"]
 ONE = ["_ZN3tgv13k_fused_tiledILi0ELi8ELi2E", "_ZN3tgv13k_fused_tiledILi1ELi4ELi2E"]
 
 
