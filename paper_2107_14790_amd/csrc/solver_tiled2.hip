@@ -361,8 +361,11 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
         }
     };
     // phase 3: dual update of plane s-1 into `out` (u+, v+, p, q of plane s-1);
-    // returns whether this column produced a result for that plane
-    auto dual = [&](L &l, Stage &S, const Pl &prev, int s, Pl &out) -> bool {
+    // returns whether this column produced a result for that plane.  p and q
+    // are rounded to the storage precision where they are computed on
+    // (stage A); stage B only stores them, and the store rounds them the
+    // same way (rounding is idempotent), so it skips the round trip.
+    auto dual = [&](L &l, Stage &S, const Pl &prev, int s, Pl &out, bool round_pq) -> bool {
         const int sv = s - 1;
         const bool do_dual = sv >= S.z0 && sv <= S.zl;
         bool made = false;
@@ -387,8 +390,10 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
             }
             for (int c = 0; c < 6; c++) out.q[c] = prev.q[c];
             dual_pq(out.p, out.q, S.UB1, ub_hi, S.VB, vb_lo, mlo, mhi, cf);
-            for (int c = 0; c < 3; c++) out.p[c] = rnd<STORE>(out.p[c]);
-            for (int c = 0; c < 6; c++) out.q[c] = rnd<STORE>(out.q[c]);
+            if (round_pq) {
+                for (int c = 0; c < 3; c++) out.p[c] = rnd<STORE>(out.p[c]);
+                for (int c = 0; c < 6; c++) out.q[c] = rnd<STORE>(out.q[c]);
+            }
             made = true;
         }
         S.UP1 = S.UP;
@@ -459,7 +464,7 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
         // result, which takes its slot two steps later, is formed)
         if (runB) {
             Pl outB;
-            if (dual(lb, B, bp, sb, outB) && in) {
+            if (dual(lb, B, bp, sb, outB, false) && in) {
                 const int sv = sb - 1;
                 const int o4 = (int)(plane4 * sv), oS = (int)(planeS * sv);
                 Io2<0>::st<SCP>(wu, v4, o4 + gu, outB.u);
@@ -470,7 +475,7 @@ __device__ __forceinline__ void run_tile2(XLds<TY> &la, XLds<TY> &lb, HLds<TY> &
                     for (int c = 0; c < 6; c++) Io2<STORE>::template st<SCP>(wq, vS, gq + oS + c * comp, outB.q[c]);
             }
         }
-        if (runA) dual(la, A, ap.f, s, bo);
+        if (runA) dual(la, A, ap.f, s, bo, true);
     };
     // No early exit inside the unrolled loop: one or two trailing steps past
     // s_end load and store nothing, and without the exits the values in flight
