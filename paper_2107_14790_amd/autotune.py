@@ -17,8 +17,8 @@ that is fastest at that pair.  A class timed alone is not the batch: in the
 mix the work queue has tiles to spare, and short chunks that fill the chip
 for one class only add halo planes there.  So the class-wise choice is
 checked on a sample of the batch itself against a few alternatives (the
-same pair with deeper or uniform chunks, the library's default) and the
-fastest of them is taken.  Results are cached per device, storage and
+same pair with chunks two or four times deeper, or uniform chunks of 32, 64
+or 128 planes, and the library's default) and the fastest of them is taken.  Results are cached per device, storage and
 class.  The measurements are function arguments, so the search itself runs
 without a GPU (tests give it a model).
 """
@@ -220,25 +220,24 @@ class Autotuner:
             idx = sorted(rng.choice(len(grids), size=min(len(grids), MIX_BLOCKS), replace=False).tolist())
             shapes = [tuple(int(v) for v in grids[i].n) for i in idx]
             tz_class = choice["tile_z_of_class"]
+            # each alternative: schedule, tile_y and a block's tile_z (None: the library's default)
+            deep = lambda k: (lambda n: min(k * tz_class[edge_class(n)], TILE_Z[-1]))
+            uniform = lambda tz: (lambda n: tz)
             alts = {
-                "class-wise": (best_sched, best_ty, [tz_class[edge_class(n)] for n in shapes]),
-                "class-wise, chunks doubled": (best_sched, best_ty, [min(2 * tz_class[edge_class(n)], TILE_Z[-1])
-                                                                     for n in shapes]),
-                "uniform chunks of 32": (best_sched, best_ty, [32] * len(shapes)),
+                "class-wise": (best_sched, best_ty, deep(1)),
+                "class-wise, chunks doubled": (best_sched, best_ty, deep(2)),
+                "class-wise, chunks quadrupled": (best_sched, best_ty, deep(4)),
+                "uniform chunks of 32": (best_sched, best_ty, uniform(32)),
+                "uniform chunks of 64": (best_sched, best_ty, uniform(64)),
+                "uniform chunks of 128": (best_sched, best_ty, uniform(128)),
                 "library default": ("fused2", 7, None),
             }
-            checked = {name: float(self.measure_mix(shapes, storage, a, b, c)) for name, (a, b, c) in alts.items()}
+            checked = {name: float(self.measure_mix(shapes, storage, a, b, None if f is None else [f(n) for n in shapes]))
+                       for name, (a, b, f) in alts.items()}
             self._release()
             win = min(checked, key=checked.get)
-            best_sched, best_ty, _ = alts[win]
-            if win == "class-wise":
-                pass
-            elif win == "class-wise, chunks doubled":
-                tile_z = [min(2 * tz_class[edge_class(g.n)], TILE_Z[-1]) for g in grids]
-            elif win == "uniform chunks of 32":
-                tile_z = [32] * len(grids)
-            else:
-                tile_z = None
+            best_sched, best_ty, f = alts[win]
+            tile_z = None if f is None else [f(tuple(int(v) for v in g.n)) for g in grids]
             checked = {"sample_blocks": len(shapes), "ms": checked, "chosen": win}
         by_schedule = {}
         for sched in SCHED_NAMES:

@@ -98,18 +98,36 @@ def test_class_wise_choice_is_checked_on_the_batch():
     mixes = []
 
     def mix_deep(shapes, storage, sched, ty, tz):
+        # four halo planes per chunk; a chunk deeper than its block is the block
         mixes.append((len(shapes), sched, ty, None if tz is None else tuple(tz)))
         vox = sum(a * b * c for a, b, c in shapes)
         if tz is None:
             return vox * 1e-6 * 1.15
-        halo = sum(a * b * c * 4.0 / t for (a, b, c), t in zip(shapes, tz))
+        halo = sum(a * b * c * 4.0 / min(t, c) for (a, b, c), t in zip(shapes, tz))
         return (vox + halo) * 1e-6
 
     r = autotune.Autotuner(measure=measure, measure_mix=mix_deep, device_name="model").tune(grids)
     assert r["schedule"] == "fused2" and r["tile_y"] == 7
-    assert r["checked_on_batch"]["chosen"] == "class-wise, chunks doubled"
-    assert r["tile_z"][0] == 16 and r["tile_z"][-1] == 64
-    assert all(n == len(grids) for n, _, _, _ in mixes) and len(mixes) == 4
+    assert r["checked_on_batch"]["chosen"] == "uniform chunks of 128"
+    assert r["tile_z"] == [128] * len(grids)
+    assert all(n == len(grids) for n, _, _, _ in mixes) and len(mixes) == 7
+    ms = r["checked_on_batch"]["ms"]
+    # deeper chunks of the class-wise choice are faster in this model, the
+    # tuned shapes beat the default, and the fastest alternative is taken
+    assert ms["class-wise"] > ms["class-wise, chunks doubled"] > ms["class-wise, chunks quadrupled"]
+    assert min(ms, key=ms.get) == "uniform chunks of 128"
+
+    def mix_doubled(shapes, storage, sched, ty, tz):
+        # the doubled class-wise chunks are the fastest shape of this batch
+        vox = sum(a * b * c for a, b, c in shapes)
+        if tz is None:
+            return vox * 1e-6 * 1.15
+        want = [min(2 * (8 if c <= 48 else 32), 128) for (a, b, c) in shapes]
+        return vox * 1e-6 * (1.0 if list(tz) == want else 1.1)
+
+    r1 = autotune.Autotuner(measure=measure, measure_mix=mix_doubled, device_name="model").tune(grids)
+    assert r1["checked_on_batch"]["chosen"] == "class-wise, chunks doubled"
+    assert r1["tile_z"][0] == 16 and r1["tile_z"][-1] == 64
 
     def mix_default(shapes, storage, sched, ty, tz):
         vox = sum(a * b * c for a, b, c in shapes)
