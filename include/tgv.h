@@ -333,7 +333,9 @@ tgv_status tgv_solve_noalloc(tgv_ctx *ctx, const tgv_grid *grid, const uint16_t 
  * per-block dual step at the start and primal step at the end; blocks too
  * large for 32-bit tile offsets run their own per-voxel launches).  hist: host array of n device pointers (block i's histograms);
  * tile_z_host: per-block z-chunk of the tiles (NULL = params->tile_z or the
- * default); params->tile_y applies to all blocks.  With TGV_FLAG_GRAPH the
+ * default: with two iterations per launch, 16, 32 or 64 planes for the whole
+ * batch, whichever a plane-step model of the batch's tiles on the device's
+ * resident workgroups finds shortest); params->tile_y applies to all blocks.  With TGV_FLAG_GRAPH the
  * iteration loop is captured once in a HIP graph and replayed.  Results are
  * bit-identical to tgv_solve on each state alone.  stats_host: NULL or n
  * entries (synchronises).  All states must use params->storage.  Open and
