@@ -850,7 +850,7 @@ extern "C" tgv_status tgv_solve_noalloc(tgv_ctx *ctx, const tgv_grid *grid, cons
 // resident workgroup plus one tile for the tail.  The depth in {16, 32, 64}
 // minimising that is taken (ties: the deeper): many blocks take deep chunks
 // (less halo), a few small blocks shallow ones (the chip stays full).  On the
-// 512 city blocks this takes 64 planes (3.01 -> 2.89 s against 32).
+// 512 city blocks this takes 64 planes (2.88 s against 3.01 s with a fixed 32).
 static int batch2_chunk(tgv_ctx *ctx, int n, tgv_state *const *states, int storage, int ty) {
     const double slots = (double)ctx->cus * batch2_blocks_per_cu(storage, ty);
     int best = 32;
