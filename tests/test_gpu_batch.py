@@ -238,3 +238,44 @@ def test_autotuned_batch_equals_solo(ctx):
         f = fields(st)
         for k in f:
             assert np.array_equal(f[k], solo[i][k]), (i, k)
+
+
+def test_two_iteration_batch_with_a_state_beyond_one_descriptor(ctx):
+    """A float32 batch whose 280^3 block has a state of more than 2 GiB (no
+    single buffer descriptor reaches all its fields), with two small blocks:
+    the whole batch then runs the batched kernel with one descriptor per
+    field; every block equals its solo solve bit for bit."""
+    import paper_2107_14790_amd as tgv
+    say("two-iteration batch with a state beyond 2 GiB")
+    big = (280, 280, 280)
+    assert tgv.state_bytes(tgv.grid_c((0, 0, 0), 1.0, big, 0), 0) > (1 << 31)
+    nb = int(np.prod(big))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(281)
+    hist_b = torch.zeros((nb, 8), dtype=torch.int16, device="cuda")
+    hist_b[:, :7] = torch.randint(0, 3, (nb, 7), device="cuda", dtype=torch.int16, generator=gen)
+    u0_b = torch.where(torch.rand(nb, device="cuda", generator=gen) < 0.5,
+                       torch.rand(nb, device="cuda", generator=gen) * 2 - 1, torch.zeros(nb, device="cuda"))
+    small = make_blocks(11)[:2]
+    grids = [tgv.grid_c((0, 0, 0), 1.0, shape, halo) for shape, halo, _, _ in small]
+    grids.append(tgv.grid_c((0, 0, 0), 1.0, big, 0))
+    hists = [torch.from_numpy(h.view(np.int16)).cuda() for _, _, h, _ in small] + [hist_b]
+    u0s = [torch.from_numpy(u0).cuda() for _, _, _, u0 in small] + [u0_b]
+    iters = 5
+    states = []
+    for g, u0 in zip(grids, u0s):
+        st = tgv.State(ctx, g, 0)
+        st.reset(u0)
+        states.append(st)
+    ctx.solve_batch(states, hists, tgv.Params(iters=iters))
+    for i, (g, h, u0) in enumerate(zip(grids, hists, u0s)):
+        solo = tgv.State(ctx, g, 0)
+        solo.reset(u0)
+        ctx.solve(g, h, None, tgv.Params(iters=iters, schedule=tgv.SCHED_FUSED), state=solo)
+        xb, ys = states[i].export(), solo.export()
+        for k in xb:
+            assert torch.equal(xb[k], ys[k]), (i, k)
+        del xb, ys
+        solo.close()
+    for st in states:
+        st.close()
