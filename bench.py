@@ -179,7 +179,7 @@ def main():
                     help="after the timed region, copy 1 GiB once (a plain copy of known size for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+        print(json.dumps({"error": "the benchmark runs on one GPU (one process per GPU, blocks are independent); --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload in ("city_batch", "city_serve", "city_precision") and args.schedule == "auto":

@@ -50,7 +50,7 @@ typedef enum {
     TGV_E_NOMEM = 2,       /* device allocation failed */
     TGV_E_DEVICE = 3,      /* a HIP runtime call failed */
     TGV_E_OVERFLOW = 4,    /* a histogram count could exceed 65535 */
-    TGV_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+    TGV_E_UNSUPPORTED = 5  /* valid request the library does not implement */
 } tgv_status;
 
 /* One camera (80 bytes): a depth map seen through a pinhole or a 360-degree
